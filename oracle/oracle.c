@@ -1,0 +1,612 @@
+/*
+ * CPU oracle for inverse iteration with compact-WY re-orthogonalization.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, obviously correct
+ * FP64 reference of what the GPU library computes.  Only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * library never links, loads or calls it.  It shares no code, header, table or
+ * helper with the HIP path.
+ *
+ * Method: H. Ishigami, K. Kimura, Y. Nakamura, "On Implementation and
+ * Evaluation of Inverse Iteration Algorithm with compact WY Orthogonalization"
+ * (arXiv:1209.1910).  Every function names the passage it follows.  Where the
+ * paper is silent (how eigenvalues are bisected, which tridiagonal solver,
+ * random start vectors, the stop rule) the function says which reading it
+ * takes; the readings are the same ones the GPU library documents.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math, no FMA), so
+ * every floating-point operation is one IEEE binary64 round-to-nearest step
+ * in the order written.
+ *
+ * Parity status: every exported function is pinned by the CPU tests against
+ * closed forms, brute force, library routines on special cases, or exact
+ * identities of the paper; none is "parity unpinned".
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Setup: norm, cluster tolerance, Sturm pivot floor, bisection bracket.       */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double norm1;   /* ||T||_1 = max_i (|d_i| + |e_{i-1}|) + |e_i|               */
+    double tol;     /* 1e-3 * ||T||_1: Peters-Wilkinson gap (section 2.1)        */
+    double pivmin;  /* Sturm-count floor: DBL_MIN * max(1, max_i e_i^2)          */
+    double pivthr;  /* LU pivot floor: DBL_EPSILON * ||T||_1                      */
+    double gl, gu;  /* widened Gershgorin bracket: count(gl) = 0, count(gu) = n  */
+    double tnorm;   /* max(|gl|, |gu|) of the unwidened Gershgorin interval       */
+} or_params;
+
+int or_sturm_count(int n, const double *d, const double *e2, double pivmin, double sigma);
+
+/* The paper clusters eigenvalues whose distance is at most 1e-3 ||T||
+ * (section 2.1, and the test in Alg. 4); ||T|| is read as the 1-norm, which
+ * for a symmetric matrix equals the infinity norm. */
+int or_setup(int n, const double *d, const double *e, or_params *p)
+{
+    if (n < 1 || !d || !p) return -1;
+    double norm1 = 0.0, maxe2 = 0.0, gl = 0.0, gu = 0.0;
+    for (int i = 0; i < n; i++) {
+        double r = fabs(d[i]);
+        double s = 0.0;
+        if (i > 0) { r = r + fabs(e[i - 1]); s = s + fabs(e[i - 1]); }
+        if (i < n - 1) { r = r + fabs(e[i]); s = s + fabs(e[i]); }
+        double lo = d[i] - s, hi = d[i] + s;
+        if (i == 0 || r > norm1) norm1 = r;
+        if (i == 0 || lo < gl) gl = lo;
+        if (i == 0 || hi > gu) gu = hi;
+    }
+    for (int i = 0; i < n - 1; i++) {
+        double q = e[i] * e[i];
+        if (q > maxe2) maxe2 = q;
+    }
+    p->norm1 = norm1;
+    p->tol = 1.0e-3 * norm1;
+    p->pivmin = DBL_MIN * (maxe2 > 1.0 ? maxe2 : 1.0);
+    p->pivthr = DBL_EPSILON * norm1;
+    double tnorm = fabs(gl) > fabs(gu) ? fabs(gl) : fabs(gu);
+    p->tnorm = tnorm;
+
+    double *e2 = (double *)malloc(sizeof(double) * (size_t)(n > 1 ? n - 1 : 1));
+    if (!e2) return -2;
+    for (int i = 0; i < n - 1; i++) e2[i] = e[i] * e[i];
+    double w = (2.0 * DBL_EPSILON * tnorm) * (double)n + 2.0 * p->pivmin;
+    double lo = gl - w, hi = gu + w;
+    for (int t = 0; t < 64; t++) {
+        lo = gl - w;
+        hi = gu + w;
+        if (or_sturm_count(n, d, e2, p->pivmin, lo) == 0 &&
+            or_sturm_count(n, d, e2, p->pivmin, hi) == n)
+            break;
+        w = 2.0 * w;
+    }
+    free(e2);
+    p->gl = lo;
+    p->gu = hi;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Eigenvalues by bisection (the experiments take them from LAPACK's         */
+/* bisection routine, section 5.1; the recurrence below is the classical     */
+/* Sturm count of T - sigma I).                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Number of eigenvalues of T strictly below sigma: the number of negative
+ * pivots of the LDL^T factorization of T - sigma I, with pivots of magnitude
+ * at most pivmin replaced by -pivmin. */
+int or_sturm_count(int n, const double *d, const double *e2, double pivmin, double sigma)
+{
+    double q = d[0] - sigma;
+    if (fabs(q) <= pivmin) q = -pivmin;
+    int cnt = q < 0.0 ? 1 : 0;
+    for (int i = 1; i < n; i++) {
+        double t1 = d[i] - sigma;
+        double t2 = e2[i - 1] / q;
+        q = t1 - t2;
+        if (fabs(q) <= pivmin) q = -pivmin;
+        if (q < 0.0) cnt++;
+    }
+    return cnt;
+}
+
+/* lambda_k for k = il..iu (1-based, inclusive) into W[0..iu-il].
+ * Plain bisection from [gl, gu] until the bracket is at most
+ * 2 eps tnorm wide (at most 128 halvings); the value is the bracket midpoint. */
+int or_bisect(int n, const double *d, const double *e, int il, int iu, double *W)
+{
+    if (n < 1 || il < 1 || iu < il || iu > n) return -1;
+    or_params p;
+    if (or_setup(n, d, e, &p)) return -2;
+    double *e2 = (double *)malloc(sizeof(double) * (size_t)(n > 1 ? n - 1 : 1));
+    if (!e2) return -2;
+    for (int i = 0; i < n - 1; i++) e2[i] = e[i] * e[i];
+    double atol = 2.0 * DBL_EPSILON * p.tnorm;
+    for (int k = il; k <= iu; k++) {
+        double lo = p.gl, hi = p.gu;
+        for (int it = 0; it < 128 && (hi - lo) > atol; it++) {
+            double mid = lo + 0.5 * (hi - lo);
+            if (or_sturm_count(n, d, e2, p.pivmin, mid) >= k) hi = mid;
+            else lo = mid;
+        }
+        W[k - il] = lo + 0.5 * (hi - lo);
+    }
+    free(e2);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Peters-Wilkinson clusters (section 2.1, Alg. 1 and Alg. 4): eigenvalue j */
+/* joins the cluster of j-1 when lambda_j - lambda_{j-1} <= tol.             */
+/* ------------------------------------------------------------------------- */
+
+int or_clusters(int m, const double *W, double tol, int *start, int *size)
+{
+    int ncl = 0;
+    for (int j = 0; j < m; j++) {
+        if (j == 0 || (W[j] - W[j - 1]) > tol) {
+            start[ncl] = j;
+            size[ncl] = 1;
+            ncl++;
+        } else {
+            size[ncl - 1]++;
+        }
+    }
+    return ncl;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Random start vectors (Alg. 1 and Alg. 4 start each v^(0) at random).      */
+/* Reading: entry i of the start vector of global eigenvalue index k is       */
+/* 2u - 1 with u = (z >> 11) 2^-53 and z the (key+1)-th output of a           */
+/* SplitMix64 stream (Steele, Lea, Flood, OOPSLA 2014) seeded with `seed`,    */
+/* key = (k << 32) | i.                                                       */
+/* ------------------------------------------------------------------------- */
+
+uint64_t or_splitmix64(uint64_t seed, uint64_t index)
+{
+    /* index-th output (1-based) of the SplitMix64 stream seeded with `seed` */
+    uint64_t z = seed + index * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+void or_start_vector(uint64_t seed, int64_t kglob, int n, double *v)
+{
+    for (int i = 0; i < n; i++) {
+        uint64_t key = ((uint64_t)kglob << 32) | (uint64_t)(uint32_t)i;
+        uint64_t z = or_splitmix64(seed, key + 1);
+        double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+        v[i] = 2.0 * u - 1.0;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Solving (T - lambda I) v^(k) = v^(k-1) (Eq. (1)).  Reading: Gaussian        */
+/* elimination with partial pivoting on the tridiagonal matrix, giving        */
+/* P (T - sigma I) = L U with U upper triangular with three diagonals          */
+/* (u1, u2, u3) and unit lower bidiagonal L (multipliers l).  A pivot of      */
+/* magnitude below pivthr is replaced by +-pivthr (sign of the pivot, + for 0) */
+/* ------------------------------------------------------------------------- */
+
+void or_lu(int n, const double *d, const double *e, double sigma, double pivthr,
+           double *u1, double *u2, double *u3, double *l, unsigned char *swp)
+{
+    double alpha = d[0] - sigma;             /* active row, column i     */
+    double beta = n > 1 ? e[0] : 0.0;        /* active row, column i + 1 */
+    for (int i = 0; i < n - 1; i++) {
+        double b = e[i];                                  /* row i+1, col i   */
+        double a1 = d[i + 1] - sigma;                     /* row i+1, col i+1 */
+        double b1 = (i + 1 < n - 1) ? e[i + 1] : 0.0;     /* row i+1, col i+2 */
+        if (fabs(alpha) >= fabs(b)) {
+            double piv = alpha;
+            if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+            u1[i] = piv; u2[i] = beta; u3[i] = 0.0; swp[i] = 0;
+            l[i] = b / piv;
+            alpha = a1 - l[i] * beta;
+            beta = b1;
+        } else {
+            double piv = b;
+            if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+            u1[i] = piv; u2[i] = a1; u3[i] = b1; swp[i] = 1;
+            l[i] = alpha / piv;
+            alpha = beta - l[i] * a1;
+            beta = -(l[i] * b1);
+        }
+    }
+    double piv = alpha;
+    if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+    u1[n - 1] = piv; u2[n - 1] = 0.0; u3[n - 1] = 0.0; l[n - 1] = 0.0; swp[n - 1] = 0;
+}
+
+/* x = U^{-1} L^{-1} P b, in place in b.  y is n doubles of scratch. */
+void or_lu_solve(int n, const double *u1, const double *u2, const double *u3,
+                 const double *l, const unsigned char *swp, double *b, double *y)
+{
+    double cur = b[0];
+    for (int i = 0; i < n - 1; i++) {
+        if (!swp[i]) { y[i] = cur; cur = b[i + 1] - l[i] * cur; }
+        else         { y[i] = b[i + 1]; cur = cur - l[i] * b[i + 1]; }
+    }
+    y[n - 1] = cur;
+    b[n - 1] = y[n - 1] / u1[n - 1];
+    if (n > 1) b[n - 2] = (y[n - 2] - u2[n - 2] * b[n - 1]) / u1[n - 2];
+    for (int i = n - 3; i >= 0; i--)
+        b[i] = ((y[i] - u2[i] * b[i + 1]) - u3[i] * b[i + 2]) / u1[i];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Small dense helpers (plain loops).                                          */
+/* ------------------------------------------------------------------------- */
+
+static double nrm2(int n, const double *x)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s = s + x[i] * x[i];
+    return sqrt(s);
+}
+
+static double sgn(double a) { return a >= 0.0 ? 1.0 : -1.0; }   /* sgn(0) = +1 */
+
+/* ------------------------------------------------------------------------- */
+/* Orthogonalization of one incoming vector against the reflectors of the     */
+/* previous c vectors.  Y is n x M column-major (ld ldy), T is M x M          */
+/* column-major upper triangular (ld ldt).  On entry v holds v_j; on exit it  */
+/* holds q_j and column c of Y, T (the paper's index j = c + 1) is (re)set.   */
+/* ------------------------------------------------------------------------- */
+
+/* Householder vector of u (rows c..n-1 meaningful) as in Eq. (yt):
+ * c_j = -sgn(u_jj) ||u_{j:n}||, y = [0; u_jj - c_j; u_{j+1:n}].
+ * Reading for ||u_{j:n}|| = 0 (the paper is silent): H = I, i.e. y = 0, t = 0.
+ * Writes column c of Y; returns c_j and (through uj) u_jj. */
+static double house_vec(int n, int c, const double *u, double *ycol, double *uj)
+{
+    double alpha = u[c];
+    double beta = nrm2(n - c, u + c);
+    double gamma = -sgn(alpha) * beta;
+    for (int i = 0; i < c; i++) ycol[i] = 0.0;
+    if (beta == 0.0) {
+        for (int i = c; i < n; i++) ycol[i] = 0.0;
+    } else {
+        for (int i = c; i < n; i++) ycol[i] = u[i];
+        ycol[c] = alpha - gamma;
+    }
+    *uj = alpha;
+    return gamma;
+}
+
+/* New implementation, section 3.3.2: only rows j..n of u_j are formed, Y is
+ * split as [L; Yhat], t_j = 1/(c_j^2 - u_jj c_j), the T column uses only Yhat,
+ * and q_j = (Y_j T_j Y_j^T - I) e_j.  The x_j <- T_j^T x_j step printed in
+ * that section is read as x_j <- T_j x_j, as Eq. (cwy2) and line 8 of Alg. 3
+ * require. */
+static void orth_cwy_new(int n, int c, double *Y, int ldy, double *T, int ldt, double *v,
+                         double *w)
+{
+    double *vchk = w;           /* c     */
+    double *tmp = w + n;        /* c     */
+    double *uh = w + 2 * n;     /* n     */
+    double *x = w + 3 * n;      /* c + 1 */
+    double *q = w + 4 * n;      /* n     */
+    /* u_hat <- v_hat (DCOPY); rows c..n-1 of uh are used */
+    for (int i = c; i < n; i++) uh[i] = v[i];
+    /* v_chk <- L^T v_chk (DTRMV, L = rows 0..c-1 of the first c columns) */
+    for (int l = 0; l < c; l++) {
+        double s = 0.0;
+        for (int i = l; i < c; i++) s = s + Y[i + (size_t)l * ldy] * v[i];
+        vchk[l] = s;
+    }
+    /* v_chk <- Yhat^T v_hat + v_chk (DGEMV) */
+    for (int l = 0; l < c; l++) {
+        double s = 0.0;
+        for (int i = c; i < n; i++) s = s + Y[i + (size_t)l * ldy] * v[i];
+        vchk[l] = s + vchk[l];
+    }
+    /* v_chk <- T^T v_chk (DTRMV, T upper) */
+    for (int l = 0; l < c; l++) {
+        double s = 0.0;
+        for (int p = 0; p <= l; p++) s = s + T[p + (size_t)l * ldt] * vchk[p];
+        tmp[l] = s;
+    }
+    for (int l = 0; l < c; l++) vchk[l] = tmp[l];
+    /* u_hat <- -Yhat v_chk + u_hat (DGEMV) */
+    for (int i = c; i < n; i++) {
+        double s = 0.0;
+        for (int l = 0; l < c; l++) s = s + Y[i + (size_t)l * ldy] * vchk[l];
+        uh[i] = uh[i] - s;
+    }
+    /* y_j and t_j (DCOPY, DNRM2) */
+    double *ycol = Y + (size_t)c * ldy;
+    double ujj;
+    double gamma = house_vec(n, c, uh, ycol, &ujj);
+    double tj = gamma == 0.0 ? 0.0 : 1.0 / (gamma * gamma - ujj * gamma);
+    /* t_hat <- (-t_j) Yhat^T y_hat (DGEMV); t_hat <- T t_hat (DTRMV) */
+    for (int l = 0; l < c; l++) {
+        double s = 0.0;
+        for (int i = c; i < n; i++) s = s + Y[i + (size_t)l * ldy] * ycol[i];
+        tmp[l] = (-tj) * s;
+    }
+    for (int p = 0; p < c; p++) {
+        double s = 0.0;
+        for (int l = p; l < c; l++) s = s + T[p + (size_t)l * ldt] * tmp[l];
+        T[p + (size_t)c * ldt] = s;
+    }
+    T[c + (size_t)c * ldt] = tj;
+    /* x_j <- row j of Y_j (DCOPY); x_j <- T_j x_j (DTRMV) */
+    for (int l = 0; l <= c; l++) x[l] = Y[c + (size_t)l * ldy];
+#ifdef OR_PRINTED_TRANSPOSE
+    /* Test-only planted mistake: the transposed product as printed. */
+    for (int l = 0; l <= c; l++) {
+        double s = 0.0;
+        for (int p = 0; p <= l; p++) s = s + T[p + (size_t)l * ldt] * x[p];
+        tmp[l] = s;
+    }
+#else
+    for (int p = 0; p <= c; p++) {
+        double s = 0.0;
+        for (int l = p; l <= c; l++) s = s + T[p + (size_t)l * ldt] * x[l];
+        tmp[p] = s;
+    }
+#endif
+    for (int p = 0; p <= c; p++) x[p] = tmp[p];
+    /* q_chk <- L_j x_j (DCOPY, DTRMV); q_hat <- Yhat_j x_j (DGEMV) */
+    for (int i = 0; i <= c; i++) {
+        double s = 0.0;
+        for (int l = 0; l <= i; l++) s = s + Y[i + (size_t)l * ldy] * x[l];
+        q[i] = s;
+    }
+    for (int i = c + 1; i < n; i++) {
+        double s = 0.0;
+        for (int l = 0; l <= c; l++) s = s + Y[i + (size_t)l * ldy] * x[l];
+        q[i] = s;
+    }
+    /* q_jj <- q_jj - 1 */
+    q[c] = q[c] - 1.0;
+    for (int i = 0; i < n; i++) v[i] = q[i];
+}
+
+/* Ordinary implementation, section 3.3.1: full-length u_j = v_j - Y T^T Y^T v_j,
+ * t_j = 2 / ||y_j||^2, t_hat = T (-t_j Y^T y_j), q_j = e_j - Y_j T_j Y_j^T e_j
+ * (again T_j where the section prints T_j^T). */
+static void orth_cwy_ordinary(int n, int c, double *Y, int ldy, double *T, int ldt, double *v,
+                              double *w)
+{
+    double *vp = w;            /* c + 1 */
+    double *tmp = w + n;       /* c + 1 */
+    double *u = w + 2 * n;     /* n     */
+    double *q = w + 4 * n;     /* n     */
+    for (int i = 0; i < n; i++) u[i] = v[i];                       /* DCOPY */
+    for (int l = 0; l < c; l++) {                                  /* DGEMV */
+        double s = 0.0;
+        for (int i = 0; i < n; i++) s = s + Y[i + (size_t)l * ldy] * u[i];
+        vp[l] = s;
+    }
+    for (int l = 0; l < c; l++) {                                  /* DTRMV T^T */
+        double s = 0.0;
+        for (int p = 0; p <= l; p++) s = s + T[p + (size_t)l * ldt] * vp[p];
+        tmp[l] = s;
+    }
+    for (int i = 0; i < n; i++) {                                  /* DGEMV */
+        double s = 0.0;
+        for (int l = 0; l < c; l++) s = s + Y[i + (size_t)l * ldy] * tmp[l];
+        u[i] = u[i] - s;
+    }
+    double *ycol = Y + (size_t)c * ldy;
+    double ujj;
+    house_vec(n, c, u, ycol, &ujj);
+    double ny = nrm2(n, ycol);
+    double tj = ny == 0.0 ? 0.0 : 2.0 / (ny * ny);
+    for (int l = 0; l < c; l++) {                                  /* DGEMV */
+        double s = 0.0;
+        for (int i = 0; i < n; i++) s = s + Y[i + (size_t)l * ldy] * ycol[i];
+        tmp[l] = (-tj) * s;
+    }
+    for (int p = 0; p < c; p++) {                                  /* DTRMV T */
+        double s = 0.0;
+        for (int l = p; l < c; l++) s = s + T[p + (size_t)l * ldt] * tmp[l];
+        T[p + (size_t)c * ldt] = s;
+    }
+    T[c + (size_t)c * ldt] = tj;
+    for (int l = 0; l <= c; l++) vp[l] = Y[c + (size_t)l * ldy];   /* DCOPY row j */
+    for (int p = 0; p <= c; p++) {                                 /* DTRMV T_j */
+        double s = 0.0;
+        for (int l = p; l <= c; l++) s = s + T[p + (size_t)l * ldt] * vp[l];
+        tmp[p] = s;
+    }
+    for (int i = 0; i < n; i++) q[i] = (i == c) ? 1.0 : 0.0;       /* DCOPY e_j */
+    for (int i = 0; i < n; i++) {                                  /* DGEMV */
+        double s = 0.0;
+        for (int l = 0; l <= c; l++) s = s + Y[i + (size_t)l * ldy] * tmp[l];
+        q[i] = q[i] - s;
+    }
+    for (int i = 0; i < n; i++) v[i] = q[i];
+}
+
+/* Householder orthogonalization, Alg. 2: apply H_1 .. H_{j-1} one at a time,
+ * form y_j, t_j = 2/||y_j||^2 from u_j, then q_j = H_1 ... H_j e_j.  Only the
+ * reflector vectors (columns of Y) and their t (diagonal of T) are used. */
+static void orth_householder(int n, int c, double *Y, int ldy, double *T, int ldt, double *v,
+                             double *w)
+{
+    double *u = w + 2 * n;
+    double *q = w + 4 * n;
+    for (int i = 0; i < n; i++) u[i] = v[i];
+    for (int r = 0; r < c; r++) {
+        const double *y = Y + (size_t)r * ldy;
+        double t = T[r + (size_t)r * ldt];
+        double s = 0.0;
+        for (int i = 0; i < n; i++) s = s + y[i] * u[i];
+        for (int i = 0; i < n; i++) u[i] = u[i] - (t * s) * y[i];
+    }
+    double *ycol = Y + (size_t)c * ldy;
+    double ujj;
+    house_vec(n, c, u, ycol, &ujj);
+    double ny = nrm2(n, ycol);
+    double tj = ny == 0.0 ? 0.0 : 2.0 / (ny * ny);
+    T[c + (size_t)c * ldt] = tj;
+    for (int i = 0; i < n; i++) q[i] = (i == c) ? 1.0 : 0.0;
+    for (int r = c; r >= 0; r--) {
+        const double *y = Y + (size_t)r * ldy;
+        double t = T[r + (size_t)r * ldt];
+        double s = 0.0;
+        for (int i = 0; i < n; i++) s = s + y[i] * q[i];
+        for (int i = 0; i < n; i++) q[i] = q[i] - (t * s) * y[i];
+    }
+    for (int i = 0; i < n; i++) v[i] = q[i];
+}
+
+enum { OR_CWY_NEW = 0, OR_CWY_ORDINARY = 1, OR_HOUSEHOLDER = 2, OR_MGS = 3 };
+
+/* Householder vector and t of the first vector of a sequence (Alg. 3 line 1). */
+static void orth_first(int n, int variant, double *Y, int ldy, double *T, int ldt,
+                       const double *u)
+{
+    double ujj;
+    double gamma = house_vec(n, 0, u, Y, &ujj);
+    double tj;
+    if (variant == OR_CWY_NEW) {
+        tj = gamma == 0.0 ? 0.0 : 1.0 / (gamma * gamma - ujj * gamma);
+    } else {
+        double ny = nrm2(n, Y);
+        tj = ny == 0.0 ? 0.0 : 2.0 / (ny * ny);
+    }
+    T[0] = tj;
+    (void)ldy; (void)ldt;
+}
+
+/* Incremental orthogonalization of the columns of V (section 3, all vectors
+ * given in advance): Q[:, j] from V[:, 0..j].  Y (n x m) and T (m x m) receive
+ * the compact-WY factors for the cWY variants (only diag(T) for Householder).
+ * variant: 0 new cWY (3.3.2), 1 ordinary cWY (3.3.1), 2 Householder (Alg. 2),
+ * 3 MGS. */
+int or_orthogonalize(int n, int m, const double *V, int ldv, double *Q, int ldq,
+                     double *Y, double *T, int variant)
+{
+    if (n < 1 || m < 1 || m > n) return -1;
+    double *w = (double *)calloc((size_t)5 * n + 8, sizeof(double));
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!w || !v) { free(w); free(v); return -2; }
+    memset(Y, 0, sizeof(double) * (size_t)n * m);
+    memset(T, 0, sizeof(double) * (size_t)m * m);
+    for (int j = 0; j < m; j++) {
+        for (int i = 0; i < n; i++) v[i] = V[i + (size_t)j * ldv];
+        if (variant == OR_MGS) {
+            for (int r = 0; r < j; r++) {
+                double s = 0.0;
+                for (int i = 0; i < n; i++) s = s + v[i] * Q[i + (size_t)r * ldq];
+                for (int i = 0; i < n; i++) v[i] = v[i] - s * Q[i + (size_t)r * ldq];
+            }
+            double nv = nrm2(n, v);
+            for (int i = 0; i < n; i++) Q[i + (size_t)j * ldq] = v[i] / nv;
+            continue;
+        }
+        if (j == 0) {
+            /* Alg. 3 lines 1-3: y_1, t_1 from u_1 = v_1, q_1 = (I - Y_1 T_1 Y_1^T) e_1 */
+            orth_first(n, variant, Y, n, T, m, v);
+            double t = T[0];
+            for (int i = 0; i < n; i++) Q[i] = -(t * Y[0]) * Y[i];
+            Q[0] = Q[0] + 1.0;
+            if (variant == OR_CWY_NEW)              /* section 3.3.2 sign of q_j */
+                for (int i = 0; i < n; i++) Q[i] = -Q[i];
+            continue;
+        }
+        if (variant == OR_CWY_NEW) orth_cwy_new(n, j, Y, n, T, m, v, w);
+        else if (variant == OR_CWY_ORDINARY) orth_cwy_ordinary(n, j, Y, n, T, m, v, w);
+        else orth_householder(n, j, Y, n, T, m, v, w);
+        for (int i = 0; i < n; i++) Q[i + (size_t)j * ldq] = v[i];
+    }
+    free(w);
+    free(v);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Inverse iteration, Alg. 4 (compact WY) and Alg. 1 (MGS).                    */
+/* ------------------------------------------------------------------------- */
+
+/* Computes eigenvectors Z[:, j] (column-major, ld ldz) of T = tridiag(e, d, e)
+ * for the m eigenvalues W[0..m-1] (ascending).  If Win is NULL they are the
+ * bisection eigenvalues il..iu and are written to W; otherwise W = Win and
+ * il is only the base of the start-vector key (eigenvalue j uses key index
+ * il + j).  orth: 0 new cWY (Alg. 4 with section 3.3.2), 1 ordinary cWY,
+ * 2 Householder, 3 MGS (Alg. 1).  iters: fixed iteration count (the paper
+ * leaves the stop test of the repeat loop open; it is read as a fixed count).  Each output
+ * column is normalized to unit 2-norm and its largest-magnitude entry (lowest
+ * index on ties) made positive.  Returns the number of clusters, or < 0. */
+int or_eigvecs(int n, const double *d, const double *e, int il, int iu, const double *Win,
+               int orth, int iters, uint64_t seed, double *W, double *Z, int ldz)
+{
+    if (n < 1 || il < 1 || iu < il || ldz < n) return -1;
+    if (!Win && iu > n) return -1;
+    int m = iu - il + 1;
+    if (m > n) return -1;
+    or_params p;
+    if (or_setup(n, d, e, &p)) return -2;
+    if (Win) { for (int j = 0; j < m; j++) W[j] = Win[j]; }
+    else if (or_bisect(n, d, e, il, iu, W)) return -2;
+
+    int *cst = (int *)malloc(sizeof(int) * (size_t)m);
+    int *csz = (int *)malloc(sizeof(int) * (size_t)m);
+    double *u1 = (double *)malloc(sizeof(double) * (size_t)n * 5);
+    unsigned char *swp = (unsigned char *)malloc((size_t)n);
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    double *w = (double *)calloc((size_t)5 * n + 8, sizeof(double));
+    if (!cst || !csz || !u1 || !swp || !v || !y || !w) return -2;
+    double *u2 = u1 + n, *u3 = u1 + 2 * (size_t)n, *lm = u1 + 3 * (size_t)n;
+    int ncl = or_clusters(m, W, p.tol, cst, csz);
+
+    int maxsz = 1;
+    for (int c = 0; c < ncl; c++) if (csz[c] > maxsz) maxsz = csz[c];
+    double *Y = (double *)calloc((size_t)n * maxsz, sizeof(double));
+    double *T = (double *)calloc((size_t)maxsz * maxsz, sizeof(double));
+    if (!Y || !T) return -2;
+
+    for (int cl = 0; cl < ncl; cl++) {
+        int j1 = cst[cl];
+        for (int j = j1; j < j1 + csz[cl]; j++) {
+            int jc = j - j1;                     /* position in the cluster */
+            or_lu(n, d, e, W[j], p.pivthr, u1, u2, u3, lm, swp);
+            or_start_vector(seed, (int64_t)il + j, n, v);
+            for (int k = 1; k <= iters; k++) {
+                double nv = nrm2(n, v);          /* normalize v^(k-1) */
+                for (int i = 0; i < n; i++) v[i] = v[i] / nv;
+                or_lu_solve(n, u1, u2, u3, lm, swp, v, y);   /* Eq. (1) */
+                if (jc == 0) continue;
+                if (orth == OR_MGS) {            /* Alg. 1: MGS against v_{j1}..v_{j-1} */
+                    for (int r = j1; r < j; r++) {
+                        const double *zr = Z + (size_t)r * ldz;
+                        double s = 0.0;
+                        for (int i = 0; i < n; i++) s = s + v[i] * zr[i];
+                        for (int i = 0; i < n; i++) v[i] = v[i] - s * zr[i];
+                    }
+                    continue;
+                }
+                if (jc == 1 && k == 1)           /* Alg. 4: Y_1, T_1 from v_{j1} */
+                    orth_first(n, orth, Y, n, T, maxsz, Z + (size_t)j1 * ldz);
+                if (orth == OR_CWY_NEW) orth_cwy_new(n, jc, Y, n, T, maxsz, v, w);
+                else if (orth == OR_CWY_ORDINARY) orth_cwy_ordinary(n, jc, Y, n, T, maxsz, v, w);
+                else orth_householder(n, jc, Y, n, T, maxsz, v, w);
+            }
+            double nv = nrm2(n, v);              /* normalize v^(k) to v_j */
+            double *z = Z + (size_t)j * ldz;
+            for (int i = 0; i < n; i++) z[i] = v[i] / nv;
+        }
+    }
+    /* Output sign: largest-magnitude entry positive (lowest index on ties).
+     * Applied after all clusters so that Y_1 is built from the unflipped
+     * normalized vector, as the GPU library does. */
+    for (int j = 0; j < m; j++) {
+        double *z = Z + (size_t)j * ldz;
+        int im = 0;
+        for (int i = 1; i < n; i++) if (fabs(z[i]) > fabs(z[im])) im = i;
+        if (z[im] < 0.0) for (int i = 0; i < n; i++) z[i] = -z[i];
+    }
+    free(cst); free(csz); free(u1); free(swp); free(v); free(y); free(w); free(Y); free(T);
+    return ncl;
+}

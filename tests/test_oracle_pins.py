@@ -1,0 +1,404 @@
+"""Pins for the CPU oracle against facts that do not come from the oracle itself.
+
+Each test cites what fixes the expected value: a published generator output,
+a textbook closed form, brute force on a tiny input, a library routine on a
+special case, or an exact identity stated in arXiv:1209.1910 (sections 3.1-3.3,
+Eq. (cwy1), Eq. (cwy2), Table 1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+from scipy.linalg import eigh_tridiagonal, eigvalsh_tridiagonal, solve_banded
+
+import oracle as O
+from paper_1209_1910_amd import inputs as G
+from tests._helpers import (align_signs, clusters_from, dense, jacobi_eigh, laplacian_eigs,
+                            laplacian_vectors, mp_eigh, orthogonality, residual, sin_angles,
+                            subspace_sin)
+
+EPS = np.finfo(np.float64).eps
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --- start vectors ------------------------------------------------------------
+
+def test_splitmix64_published_outputs():
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "splitmix64.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) >= 8
+    for seed, idx, out in rows:
+        assert O.splitmix64(int(seed), int(idx)) == int(out)
+
+
+def test_start_vector_range_and_keying():
+    v = O.start_vector(7, 3, 20000)
+    assert v.min() >= -1.0 and v.max() < 1.0
+    assert abs(v.mean()) < 0.02 and abs(v.var() - 1.0 / 3.0) < 0.02
+    # entry i of eigenvalue k depends only on (seed, k, i): prefixes agree
+    assert np.array_equal(O.start_vector(7, 3, 50), v[:50])
+    assert not np.array_equal(O.start_vector(7, 4, 50), v[:50])
+    # the first entry of key (k=0, i=0) is output 1 of the stream: 2u-1 with u from its top 53 bits
+    z = O.splitmix64(0, 1)
+    assert O.start_vector(0, 0, 1)[0] == 2.0 * ((z >> 11) * 2.0 ** -53) - 1.0
+
+
+# --- norm / setup ---------------------------------------------------------------
+
+def test_setup_norm_and_bracket():
+    d, e = G.uniform_tridiag(257, 11)
+    p = O.setup(d, e)
+    assert p.norm1 == np.max(np.abs(dense(d, e)).sum(axis=1))
+    assert p.tol == 1e-3 * p.norm1
+    assert O.sturm_count(d, e, p.gl) == 0 and O.sturm_count(d, e, p.gu) == len(d)
+    w = np.linalg.eigvalsh(dense(d, e))
+    assert p.gl < w[0] and p.gu > w[-1]
+
+
+# --- Sturm counts ----------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 50, 301, 1000])
+def test_sturm_count_laplacian_closed_form(n):
+    """count(sigma) = #{k : 2 - 2 cos(k pi/(n+1)) < sigma} exactly at midpoints."""
+    d, e = G.laplacian_tridiag(n)
+    lam = laplacian_eigs(n)
+    mids = np.concatenate([[lam[0] - 0.5], 0.5 * (lam[:-1] + lam[1:]), [lam[-1] + 0.5]])
+    for idx, s in enumerate(mids):
+        assert O.sturm_count(d, e, s) == idx
+
+
+def test_sturm_count_monotone_random():
+    d, e = G.uniform_tridiag(400, 5)
+    p = O.setup(d, e)
+    sig = np.sort(np.random.default_rng(0).uniform(p.gl, p.gu, 600))
+    c = [O.sturm_count(d, e, s) for s in sig]
+    assert all(a <= b for a, b in zip(c, c[1:]))
+    assert c[0] >= 0 and c[-1] <= 400
+
+
+def test_wilkinson_w21_against_bruteforce():
+    d, e = G.wilkinson_w21()
+    mu, _ = mp_eigh(dense(d, e))            # 40-digit brute force
+    muj, _ = jacobi_eigh(dense(d, e))       # float64 Jacobi
+    assert np.max(np.abs(mu - muj)) <= 8 * EPS * 11.0
+    W = O.bisect(d, e)
+    assert np.max(np.abs(W - mu)) <= 8 * EPS * 11.0
+
+
+def test_glued_wilkinson_count_weyl():
+    """Weyl: each glued eigenvalue is within delta of blockdiag(W21 x g), so
+    count(sigma) = g * #{mu_l < sigma} whenever sigma is farther than delta
+    from every W21 eigenvalue mu_l."""
+    g, delta = 30, 1e-8
+    d, e = G.glued_wilkinson(g, delta)
+    mu, _ = jacobi_eigh(dense(*G.wilkinson_w21()))
+    gaps = np.diff(mu)
+    for l in range(20):
+        if gaps[l] > 4 * delta:
+            s = 0.5 * (mu[l] + mu[l + 1])
+            assert O.sturm_count(d, e, s) == g * (l + 1)
+    assert O.sturm_count(d, e, mu[0] - 1.0) == 0
+    assert O.sturm_count(d, e, mu[-1] + 1.0) == 21 * g
+
+
+# --- bisection ----------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 7, 100, 1000])
+def test_bisect_laplacian_closed_form(n):
+    d, e = G.laplacian_tridiag(n)
+    W = O.bisect(d, e)
+    norm1 = O.setup(d, e).norm1
+    assert np.max(np.abs(W - laplacian_eigs(n))) <= 8 * EPS * norm1
+
+
+def test_bisect_n2_closed_form():
+    d = np.array([0.3, -1.1])
+    e = np.array([0.7])
+    mid, rad = 0.5 * (d[0] + d[1]), np.hypot(0.5 * (d[0] - d[1]), e[0])
+    W = O.bisect(d, e)
+    assert np.allclose(W, [mid - rad, mid + rad], atol=8 * EPS * 1.8)
+
+
+def test_bisect_vs_lapack_stebz():
+    d, e = G.workload_small()
+    W = O.bisect(d, e)
+    ws = eigvalsh_tridiagonal(d, e, lapack_driver="stebz")
+    assert np.max(np.abs(W - ws)) <= 4 * EPS * O.setup(d, e).norm1
+
+
+def test_bisect_subrange_matches_full():
+    d, e = G.uniform_tridiag(300, 3)
+    full = O.bisect(d, e)
+    assert np.array_equal(O.bisect(d, e, 40, 77), full[39:77])
+
+
+def test_bisect_bruteforce_small():
+    for seed in range(3):
+        d, e = G.uniform_tridiag(32, 100 + seed)
+        w, _ = mp_eigh(dense(d, e))
+        W = O.bisect(d, e)
+        assert np.max(np.abs(W - w)) <= 4 * EPS * O.setup(d, e).norm1
+
+
+# --- clusters -------------------------------------------------------------------------
+
+def test_clusters_rule_and_laplacian_single_cluster():
+    # n >= 1571: every gap 2 - 2cos is below 4 sin(pi/(2(n+1))) < 1e-3 * ||T||_1 = 4e-3
+    d, e = G.laplacian_tridiag(2000)
+    W = O.bisect(d, e)
+    st, sz = O.clusters(W, O.setup(d, e).tol)
+    assert len(st) == 1 and sz[0] == 2000
+    # rule: new cluster iff gap > tol (a gap equal to tol stays in the cluster)
+    st, sz = O.clusters(np.array([0.0, 1.0, 2.0, 3.5]), 1.0)
+    assert list(st) == [0, 3] and list(sz) == [3, 1]
+
+
+def test_clusters_glued_wilkinson_structure():
+    """The 21 groups of g close eigenvalues merge into 14 clusters under the
+    chain rule: seven W21 near-pairs are split by less than 1e-3 ||T||_1."""
+    g = 24
+    d, e = G.glued_wilkinson(g, 1e-8)
+    W = O.bisect(d, e)
+    tol = O.setup(d, e).tol
+    st, sz = O.clusters(W, tol)
+    mu, _ = jacobi_eigh(dense(*G.wilkinson_w21()))
+    groups = [(s, c * g) for s, c in clusters_from(mu, tol)]
+    assert [c for _, c in groups] == list(sz)
+    assert len(sz) == 14 and sorted(set(sz)) == [g, 2 * g]
+
+
+# --- LU with partial pivoting and the solve of Eq. (1) -------------------------------
+
+def test_lu_solve_vs_banded_library():
+    d, e = G.uniform_tridiag(500, 8)
+    p = O.setup(d, e)
+    sigma = 0.123456
+    f = O.lu(d, e, sigma, p.pivthr)
+    u1, u2, u3, l, swp = f
+    assert np.all(np.abs(l[:-1]) <= 1.0)
+    assert np.all(np.abs(u1[:-1]) >= np.abs(e) * (1 - 1e-15))   # partial pivoting
+    b = np.random.default_rng(1).standard_normal(500)
+    x = O.lu_solve(f, b)
+    ab = np.zeros((3, 500))
+    ab[0, 1:] = e
+    ab[1] = d - sigma
+    ab[2, :-1] = e
+    xr = solve_banded((1, 1), ab, b)
+    assert np.max(np.abs(x - xr)) <= 1e-11 * np.max(np.abs(xr))
+    r = dense(d, e) @ x - sigma * x - b
+    assert np.linalg.norm(r) <= 1e-13 * p.norm1 * np.linalg.norm(x)
+
+
+def test_lu_solve_near_eigenvalue_points_at_eigenvector():
+    n = 300
+    d, e = G.laplacian_tridiag(n)
+    p = O.setup(d, e)
+    k = 17
+    lam = laplacian_eigs(n)[k]
+    f = O.lu(d, e, lam, p.pivthr)
+    x = O.lu_solve(f, O.start_vector(1, 1, n))
+    x /= np.linalg.norm(x)
+    z = laplacian_vectors(n, [k])[:, 0]
+    assert sin_angles(x[:, None], z[:, None])[0] < 1e-10
+
+
+def test_lu_n1():
+    f = O.lu(np.array([3.0]), np.array([]), 1.0, 1e-16)
+    assert O.lu_solve(f, np.array([4.0]))[0] == 2.0
+
+
+# --- compact WY identities (sections 3.1-3.3) ----------------------------------------
+
+def _random_V(n, m, seed, cond=None):
+    rng = np.random.default_rng(seed)
+    V = rng.standard_normal((n, m))
+    if cond is not None:
+        U, _, Wt = np.linalg.svd(V, full_matrices=False)
+        s = np.logspace(0, -np.log10(cond), m)
+        V = (U * s) @ Wt
+    return V
+
+
+@pytest.mark.parametrize("n,m", [(9, 5), (40, 40), (120, 33)])
+def test_cwy_equals_householder_qr(n, m):
+    """Alg. 3 produces q_j = H_1...H_j e_j with c_j = -sgn(u_jj)||u||, which is
+    the Q factor of the Householder QR of V with LAPACK's sign convention; the
+    new implementation returns -q_j (section 3.3.2)."""
+    V = _random_V(n, m, n + m)
+    Qr, _ = np.linalg.qr(V)
+    Q1, _, _ = O.orthogonalize(V, O.CWY_ORDINARY)
+    Q0, _, _ = O.orthogonalize(V, O.CWY_NEW)
+    Q2, _, _ = O.orthogonalize(V, O.HOUSEHOLDER)
+    if m == n:
+        # LAPACK takes H = I when the column has nothing below the diagonal,
+        # Eq. (yt) still reflects (c_n = -sgn(u_nn)|u_nn|): that column flips sign.
+        Qr[:, -1] = -Qr[:, -1]
+    assert np.max(np.abs(Q1 - Qr)) < 1e-12
+    assert np.max(np.abs(Q2 - Qr)) < 1e-12
+    assert np.max(np.abs(Q0 + Qr)) < 1e-12
+
+
+def test_cwy2_product_of_reflectors():
+    """Eq. (cwy2): H_1 H_2 ... H_j = I - Y_j T_j Y_j^T, with H_i = I - t_i y_i y_i^T
+    and t_i = 2 / ||y_i||^2 (Eq. (yt); section 3.3.2 shows t = 1/(c^2 - u c))."""
+    n, m = 30, 12
+    V = _random_V(n, m, 3)
+    _, Y, T = O.orthogonalize(V, O.CWY_NEW)
+    for i in range(m):
+        assert abs(T[i, i] - 2.0 / np.dot(Y[:, i], Y[:, i])) <= 1e-14 * T[i, i]
+        assert np.all(Y[:i, i] == 0.0)
+    assert np.all(np.tril(T, -1) == 0.0)
+    P = np.eye(n)
+    for j in range(m):
+        P = P @ (np.eye(n) - T[j, j] * np.outer(Y[:, j], Y[:, j]))
+        Yj, Tj = Y[:, :j + 1], T[:j + 1, :j + 1]
+        assert np.max(np.abs(P - (np.eye(n) - Yj @ Tj @ Yj.T))) < 1e-13
+
+
+def test_cwy1_t_column_recursion():
+    """Eq. (cwy1): the new column of T_j is -t_j T_{j-1} Y_{j-1}^T y_j."""
+    n, m = 25, 10
+    _, Y, T = O.orthogonalize(_random_V(n, m, 4), O.CWY_NEW)
+    for j in range(1, m):
+        ref = -T[j, j] * T[:j, :j] @ (Y[:, :j].T @ Y[:, j])
+        assert np.max(np.abs(T[:j, j] - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_table1_orthogonality_mgs_vs_cwy():
+    """Table 1: MGS loses orthogonality like eps * kappa(V); compact WY keeps O(eps)."""
+    V = _random_V(200, 40, 9, cond=1e11)
+    Qm, _, _ = O.orthogonalize(V, O.MGS)
+    Qc, _, _ = O.orthogonalize(V, O.CWY_NEW)
+    assert orthogonality(Qc) < 1e-13
+    assert orthogonality(Qm) > 1e-8
+
+
+def test_printed_transpose_fails_the_pins():
+    """The q-formation step is printed with T_j^T; built that way the oracle
+    no longer produces orthonormal vectors, so T_j is the only consistent reading."""
+    tmp = tempfile.mkdtemp()
+    try:
+        so = os.path.join(tmp, "libmut.so")
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-DOR_PRINTED_TRANSPOSE", "-o", so,
+                               os.path.join(os.path.dirname(O.__file__), "oracle.c"), "-lm"])
+        L = ctypes.CDLL(so)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.or_orthogonalize.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, dp,
+                                       ctypes.c_int, dp, dp, ctypes.c_int]
+        n, m = 9, 5
+        V = np.asfortranarray(_random_V(n, m, 2))
+        Q = np.zeros((n, m), order="F")
+        Y = np.zeros((n, m), order="F")
+        T = np.zeros((m, m), order="F")
+        L.or_orthogonalize(n, m, V.ctypes.data_as(dp), n, Q.ctypes.data_as(dp), n,
+                           Y.ctypes.data_as(dp), T.ctypes.data_as(dp), 0)
+        assert orthogonality(Q) > 1e-3
+    finally:
+        shutil.rmtree(tmp)
+
+
+# --- the whole method ------------------------------------------------------------------
+
+def test_laplacian_closed_form_vectors():
+    n = 400
+    d, e = G.laplacian_tridiag(n)
+    W, Z, _ = O.eigvecs(d, e)
+    Zc = laplacian_vectors(n)
+    assert np.max(sin_angles(Z, Zc)) <= 1e-9
+    assert np.max(np.abs(align_signs(Z, Zc) - Z)) <= 1e-9
+    assert residual(d, e, W, Z) <= 1e-12
+    assert orthogonality(Z) <= 1e-11
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_tiny_closed_forms(n):
+    d = np.array([0.5, -0.25][:n])
+    e = np.array([0.75][:n - 1])
+    W, Z, _ = O.eigvecs(d, e)
+    w, V = np.linalg.eigh(dense(d, e))
+    assert np.allclose(W, w, atol=1e-15)
+    assert np.allclose(np.abs(Z), np.abs(V), atol=1e-14)
+    # sign convention: largest-magnitude entry positive
+    for j in range(n):
+        assert Z[np.argmax(np.abs(Z[:, j])), j] > 0
+
+
+def test_jacobi_bruteforce_vectors():
+    for seed in range(3):
+        n = 48
+        d, e = G.uniform_tridiag(n, 200 + seed)
+        W, Z, _ = O.eigvecs(d, e)
+        w, V = jacobi_eigh(dense(d, e))
+        norm1 = O.setup(d, e).norm1
+        assert np.max(np.abs(W - w)) <= 1e-13 * norm1
+        gaps = np.minimum(np.diff(w, prepend=-np.inf), np.diff(w, append=np.inf))
+        iso = gaps >= 1e-3 * norm1
+        assert np.max(sin_angles(Z[:, iso], V[:, iso])) <= 1e-9
+
+
+@pytest.mark.parametrize("wl", ["small", "glued24", "laplacian600"])
+def test_residual_orthogonality_targets(wl):
+    if wl == "small":
+        d, e = G.workload_small()
+    elif wl == "glued24":
+        d, e = G.glued_wilkinson(24, 1e-8)
+    else:
+        d, e = G.laplacian_tridiag(600)
+    W, Z, _ = O.eigvecs(d, e)
+    assert residual(d, e, W, Z) <= 1e-12
+    assert orthogonality(Z) <= 1e-11
+
+
+def test_small_workload_cluster_facts():
+    d, e = G.workload_small()
+    W, Z, ncl = O.eigvecs(d, e)
+    st, sz = O.clusters(W, O.setup(d, e).tol)
+    assert ncl == len(st) == 471
+    assert int((sz == 1).sum()) == 230 and int(sz.max()) == 12
+
+
+def test_vectors_vs_lapack_subspaces():
+    """Library cross-check: LAPACK's tridiagonal eigenvectors span the same
+    cluster subspaces (vectors inside a cluster are not unique)."""
+    d, e = G.uniform_tridiag(600, 21)
+    W, Z, _ = O.eigvecs(d, e)
+    w, V = eigh_tridiagonal(d, e)
+    st, sz = O.clusters(W, O.setup(d, e).tol)
+    for s, c in zip(st, sz):
+        assert subspace_sin(Z[:, s:s + c], V[:, s:s + c]) <= 1e-9
+
+
+def test_variants_agree_on_subspaces():
+    d, e = G.glued_wilkinson(10, 1e-8)
+    W, Z0, _ = O.eigvecs(d, e, orth=O.CWY_NEW)
+    st, sz = O.clusters(W, O.setup(d, e).tol)
+    for orth in (O.CWY_ORDINARY, O.HOUSEHOLDER, O.MGS):
+        _, Z1, _ = O.eigvecs(d, e, orth=orth)
+        for s, c in zip(st, sz):
+            assert subspace_sin(Z0[:, s:s + c], Z1[:, s:s + c]) <= 1e-9
+
+
+def test_range_request_reuses_start_vectors():
+    d, e = G.uniform_tridiag(300, 31)
+    W, Z, _ = O.eigvecs(d, e)
+    W2, Z2, _ = O.eigvecs(d, e, il=101, iu=140)
+    assert np.array_equal(W2, W[100:140])
+    # singleton clusters are computed identically inside a range
+    st, sz = O.clusters(W, O.setup(d, e).tol)
+    for s, c in zip(st, sz):
+        if c == 1 and 100 <= s < 140:
+            assert np.array_equal(Z2[:, s - 100], Z[:, s])
+
+
+def test_given_w_matches_bisection_path():
+    d, e = G.uniform_tridiag(200, 41)
+    W, Z, _ = O.eigvecs(d, e)
+    W2, Z2, _ = O.eigvecs(d, e, W=W)
+    assert np.array_equal(W, W2) and np.array_equal(Z, Z2)
