@@ -1,0 +1,146 @@
+/*
+ * tridiag_eigvecs: eigenvectors of a real symmetric tridiagonal matrix by
+ * inverse iteration with compact-WY re-orthogonalization, on AMD Instinct
+ * MI355X (gfx950), FP64 throughout.
+ *
+ * Method: H. Ishigami, K. Kimura, Y. Nakamura, "On Implementation and
+ * Evaluation of Inverse Iteration Algorithm with compact WY Orthogonalization",
+ * arXiv:1209.1910.
+ *   - Eigenvalues: Sturm-count bisection (the experiments of section 5.1 take
+ *     the eigenvalues from bisection).
+ *   - Clusters: eigenvalue j joins the cluster of j-1 when
+ *     lambda_j - lambda_{j-1} <= 1e-3 ||T||_1 (section 2.1; Alg. 1 and 4).
+ *   - Iteration: solve (T - lambda_j I) v^(k) = v^(k-1) (Eq. (1)) after
+ *     normalizing v^(k-1), a fixed number of times (3).
+ *   - Within a cluster, each iterate is re-orthogonalized against the previous
+ *     members with the compact WY representation, Eqs. (cwy1)-(cwy2), in the
+ *     form of section 3.3.2, as Alg. 4 prescribes.
+ *
+ * Conventions for every entry point:
+ *   - T = tridiag(e, d, e): d has n entries, e has n - 1.
+ *   - Pointers named d, e, W, Z, d_all, ... are DEVICE pointers to memory the
+ *     caller allocated and owns; the library never frees or retains them after
+ *     the work it enqueued has completed.
+ *   - Work runs on `stream` (a hipStream_t; 0 is the null stream).  Between
+ *     the cluster detection and the cluster chains every eigenvector entry
+ *     point copies the cluster table to the host to plan the chains, and it
+ *     synchronizes `stream` before returning: on return the outputs are ready.
+ *   - Index ranges are LAPACK style: 1 <= il <= iu <= n, inclusive; m = iu - il + 1.
+ *   - Outputs: W[0..m-1] ascending eigenvalues lambda_il..lambda_iu; column j of
+ *     Z (column-major, leading dimension ldz >= n) is the unit-2-norm
+ *     eigenvector of W[j], its largest-magnitude entry (lowest index on ties)
+ *     made positive.
+ *   - Return value: 0 on success; -i when argument i (1-based) is invalid,
+ *     detected on the host before anything is enqueued; TE_ERR_* below on a
+ *     runtime failure (the HIP error is available from te_last_hip_error()).
+ *
+ * Start vectors: entry i of v^(0) for eigenvalue index k (1-based, global) is
+ * 2u - 1, u = (z >> 11) * 2^-53, z the (((k << 32) | i) + 1)-th output of the
+ * SplitMix64 stream seeded with `seed` (Steele, Lea, Flood, OOPSLA 2014).  The
+ * plain entry points use TE_DEFAULT_SEED.  Keying by the global index makes a
+ * range request compute, for every cluster fully inside the range, exactly the
+ * vectors of the full request.
+ */
+#ifndef TRIDIAG_EIGVECS_H
+#define TRIDIAG_EIGVECS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TE_DEFAULT_SEED 0x12091910ULL
+#define TE_DEFAULT_ITERS 3
+
+/* Runtime failures (argument errors are the negative argument position). */
+#define TE_ERR_HIP (-1000)        /* a HIP runtime call failed                   */
+#define TE_ERR_NO_DEVICE (-1001)  /* no usable gfx950 device                     */
+#define TE_ERR_WORKSPACE (-1002)  /* workspace too small / allocation failed     */
+#define TE_ERR_KERNEL (-1003)     /* a cooperative chain barrier timed out       */
+
+/* Options for the _ex entry point.  Zero-initialize and set what you need;
+ * a zero field means the default. */
+typedef struct te_opts {
+    int iters;          /* inverse-iteration steps per vector (default 3)          */
+    int _reserved0;
+    uint64_t seed;      /* start-vector seed (default TE_DEFAULT_SEED)              */
+    double cluster_rtol;/* cluster gap as a multiple of ||T||_1 (default 1e-3)      */
+    int coop_wgs;       /* cap on cooperative workgroups (0: fill the device)       */
+    int _reserved1;
+} te_opts;
+
+/* Eigenpairs il..iu of T (bisection for W, then inverse iteration).
+ * Argument positions for error codes: d=1 e=2 n=3 il=4 iu=5 W=6 Z=7 ldz=8.
+ * Allocates its workspace with hipMallocAsync on `stream` and frees it before
+ * returning (the memory pool may keep it cached). */
+int tridiag_eigvecs(const double *d, const double *e, int n, int il, int iu,
+                    double *W, double *Z, int ldz, hipStream_t stream);
+
+/* Eigenvectors for m caller-supplied eigenvalue approximations W[0..m-1]
+ * (ascending, device memory), the role the paper's DSTEIN-cWY plays after
+ * bisection (section 4).  Start vectors are keyed by k = j + 1.
+ * Argument positions: d=1 e=2 n=3 m=4 W=5 Z=6 ldz=7. */
+int tridiag_eigvecs_given_w(const double *d, const double *e, int n, int m,
+                            const double *W, double *Z, int ldz, hipStream_t stream);
+
+/* Upper bound, in bytes, of the device workspace the _ex entry point needs for
+ * one problem of order n with indices il..iu.  Returns 0 for invalid sizes. */
+size_t tridiag_eigvecs_workspace_bytes(int n, int il, int iu);
+
+/* As tridiag_eigvecs with options and a caller-provided device workspace `ws`
+ * of at least tridiag_eigvecs_workspace_bytes(n, il, iu) bytes (256-byte
+ * aligned).  If W_given is non-NULL the eigenvalues are taken from it (device,
+ * m entries, ascending) and copied to W instead of bisecting.  info (device,
+ * may be NULL) receives 1 + m ints: info[0] the number of vectors with a
+ * non-finite entry, info[1 + j] nonzero for such a vector.
+ * Argument positions: d=1 e=2 n=3 il=4 iu=5 W_given=6 W=7 Z=8 ldz=9 opt=10
+ * ws=11 ws_bytes=12 info=13. */
+int tridiag_eigvecs_ex(const double *d, const double *e, int n, int il, int iu,
+                       const double *W_given, double *W, double *Z, int ldz,
+                       const te_opts *opt, void *ws, size_t ws_bytes, int *info,
+                       hipStream_t stream);
+
+/* B independent problems in one pass.  Problem b has order
+ * n_b = off[b+1] - off[b]; its d entries are d_all[off[b] .. off[b+1]-1] and
+ * its e entries e_all[off[b] - b .. off[b+1] - b - 2] (n_b - 1 of them).
+ * il[b], iu[b] (host arrays) select its eigenvalues; W_all[woff[b] ..] receives
+ * them and Z_all + zoff[b] its eigenvectors with leading dimension n_b, where
+ * woff/zoff (host arrays of B entries) are caller-chosen offsets.  off, il, iu,
+ * woff, zoff are HOST arrays; d_all, e_all, W_all, Z_all are device arrays.
+ * All problems share one workspace allocation and one launch per phase.
+ * Argument positions: d_all=1 e_all=2 off=3 il=4 iu=5 W_all=6 woff=7 Z_all=8
+ * zoff=9 B=10 opt=11. */
+int tridiag_eigvecs_batched(const double *d_all, const double *e_all, const int64_t *off,
+                            const int *il, const int *iu, double *W_all, const int64_t *woff,
+                            double *Z_all, const int64_t *zoff, int B, const te_opts *opt,
+                            hipStream_t stream);
+
+/* Eigenvalues only: lambda_il..lambda_iu of T by Sturm-count bisection, into
+ * W[0..m-1] (device).  Counts are exact integers; W is the bracket midpoint
+ * after the bracket [gl, gu] (Gershgorin, widened until count(gl) = 0 and
+ * count(gu) = n) has been halved until it is at most 2 eps max(|gl|,|gu|)
+ * wide.  Synchronizes `stream` before returning.
+ * Argument positions: d=1 e=2 n=3 il=4 iu=5 W=6. */
+int tridiag_eigvals(const double *d, const double *e, int n, int il, int iu, double *W,
+                    hipStream_t stream);
+
+/* Peters-Wilkinson clusters of m ascending values W (device): j starts a new
+ * cluster iff j = 0 or W[j] - W[j-1] > tol (section 2.1; Alg. 1 and 4).
+ * Writes the cluster starts and sizes (device int arrays of at least m
+ * entries) and their count *ncl (device int).  Synchronizes `stream`.
+ * Argument positions: W=1 m=2 tol=3 start=4 size=5 ncl=6. */
+int tridiag_clusters(const double *W, int m, double tol, int *start, int *size, int *ncl,
+                     hipStream_t stream);
+
+/* HIP error code of the last runtime failure seen by this thread (0 if none). */
+int te_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRIDIAG_EIGVECS_H */

@@ -1,0 +1,253 @@
+"""ctypes binding of the HIP C-ABI library (argument marshalling only).
+
+Every function here forwards to the entry point of the same name in
+``libtridiag_eigvecs.so``; PyTorch provides device memory and the stream.
+There is no fallback: if the library is not built, or no GPU is present, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtridiag_eigvecs.so")
+
+TE_DEFAULT_SEED = 0x12091910
+SYMBOLS = ("tridiag_eigvecs", "tridiag_eigvecs_given_w", "tridiag_eigvecs_workspace_bytes",
+           "tridiag_eigvecs_ex", "tridiag_eigvecs_batched", "tridiag_eigvals", "tridiag_clusters",
+           "te_last_hip_error")
+
+
+class TeError(RuntimeError):
+    def __init__(self, fn, rc, hip=0):
+        super().__init__(f"{fn} returned {rc}" + (f" (hip error {hip})" if hip else ""))
+        self.rc = rc
+        self.hip = hip
+
+
+class te_opts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("_reserved0", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("cluster_rtol", ctypes.c_double),
+                ("coop_wgs", ctypes.c_int), ("_reserved1", ctypes.c_int)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        i, sz, i64p = ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.tridiag_eigvecs.argtypes = [_vp, _vp, i, i, i, _vp, _vp, i, _vp]
+        L.tridiag_eigvecs_given_w.argtypes = [_vp, _vp, i, i, _vp, _vp, i, _vp]
+        L.tridiag_eigvecs_workspace_bytes.argtypes = [i, i, i]
+        L.tridiag_eigvecs_workspace_bytes.restype = sz
+        L.tridiag_eigvecs_ex.argtypes = [_vp, _vp, i, i, i, _vp, _vp, _vp, i,
+                                         ctypes.POINTER(te_opts), _vp, sz, _vp, _vp]
+        L.tridiag_eigvecs_batched.argtypes = [_vp, _vp, i64p, ip, ip, _vp, i64p, _vp, i64p, i,
+                                              ctypes.POINTER(te_opts), _vp]
+        L.tridiag_eigvals.argtypes = [_vp, _vp, i, i, i, _vp, _vp]
+        L.tridiag_clusters.argtypes = [_vp, i, ctypes.c_double, _vp, _vp, _vp, _vp]
+        L.te_last_hip_error.restype = i
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(x, device):
+    torch = _torch()
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
+    x = x.to(device=device, dtype=torch.float64).contiguous()
+    return x
+
+
+def _host_f64(x):
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        return x.detach().to("cpu", torch.float64).numpy()
+    return np.asarray(x, dtype=np.float64)
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise TeError(fn, rc, lib().te_last_hip_error())
+
+
+def _opts(iters=None, seed=None, cluster_rtol=None, coop_wgs=None):
+    o = te_opts()
+    o.iters = int(iters or 0)
+    o.seed = int(seed or 0)
+    o.cluster_rtol = float(cluster_rtol or 0.0)
+    o.coop_wgs = int(coop_wgs or 0)
+    return o
+
+
+def tridiag_eigvecs(d, e, il=1, iu=None, stream=None, device="cuda"):
+    """Eigenpairs il..iu (1-based, inclusive) of tridiag(e, d, e).
+
+    Returns (W, Z): float64 device tensors, W of shape (m,), Z of shape (m, n)
+    whose row j is the eigenvector of W[j] (column j of the column-major
+    n x m result the library writes).
+    """
+    torch = _torch()
+    d = _dev_f64(d, device)
+    e = _dev_f64(e, device)
+    n = d.numel()
+    iu = n if iu is None else iu
+    m = iu - il + 1
+    W = torch.empty(max(m, 1), dtype=torch.float64, device=d.device)
+    Z = torch.empty((max(m, 1), n), dtype=torch.float64, device=d.device)
+    rc = lib().tridiag_eigvecs(_vp(d.data_ptr()), _vp(e.data_ptr() if e.numel() else 0), n, il, iu,
+                               _vp(W.data_ptr()), _vp(Z.data_ptr()), n, _stream_ptr(stream))
+    _check("tridiag_eigvecs", rc)
+    return W[:m], Z[:m]
+
+
+def tridiag_eigvecs_given_w(d, e, W, stream=None, device="cuda"):
+    """Eigenvectors for given ascending eigenvalue approximations W (m,).
+    Returns Z of shape (m, n) (row j = eigenvector of W[j])."""
+    torch = _torch()
+    d = _dev_f64(d, device)
+    e = _dev_f64(e, device)
+    W = _dev_f64(W, device)
+    n, m = d.numel(), W.numel()
+    Z = torch.empty((m, n), dtype=torch.float64, device=d.device)
+    rc = lib().tridiag_eigvecs_given_w(_vp(d.data_ptr()), _vp(e.data_ptr() if e.numel() else 0), n,
+                                       m, _vp(W.data_ptr()), _vp(Z.data_ptr()), n,
+                                       _stream_ptr(stream))
+    _check("tridiag_eigvecs_given_w", rc)
+    return Z
+
+
+def tridiag_eigvals(d, e, il=1, iu=None, stream=None, device="cuda"):
+    """Eigenvalues il..iu by Sturm bisection; returns a float64 device tensor."""
+    torch = _torch()
+    d = _dev_f64(d, device)
+    e = _dev_f64(e, device)
+    n = d.numel()
+    iu = n if iu is None else iu
+    m = iu - il + 1
+    W = torch.empty(max(m, 1), dtype=torch.float64, device=d.device)
+    rc = lib().tridiag_eigvals(_vp(d.data_ptr()), _vp(e.data_ptr() if e.numel() else 0), n, il, iu,
+                               _vp(W.data_ptr()), _stream_ptr(stream))
+    _check("tridiag_eigvals", rc)
+    return W[:m]
+
+
+def tridiag_clusters(W, tol, stream=None, device="cuda"):
+    """Cluster starts and sizes of ascending W under the gap rule; returns
+    (start, size) int32 device tensors of length ncl."""
+    torch = _torch()
+    W = _dev_f64(W, device)
+    m = W.numel()
+    start = torch.empty(max(m, 1), dtype=torch.int32, device=W.device)
+    size = torch.empty(max(m, 1), dtype=torch.int32, device=W.device)
+    ncl = torch.zeros(1, dtype=torch.int32, device=W.device)
+    rc = lib().tridiag_clusters(_vp(W.data_ptr()), m, float(tol), _vp(start.data_ptr()),
+                                _vp(size.data_ptr()), _vp(ncl.data_ptr()), _stream_ptr(stream))
+    _check("tridiag_clusters", rc)
+    k = int(ncl.item())
+    return start[:k], size[:k]
+
+
+def tridiag_eigvecs_workspace_bytes(n, il, iu):
+    return int(lib().tridiag_eigvecs_workspace_bytes(n, il, iu))
+
+
+def tridiag_eigvecs_ex(d, e, il=1, iu=None, W_given=None, ws=None, info=None, stream=None,
+                       device="cuda", **opts):
+    """_ex entry point.  ws: uint8 device tensor (allocated here if None).
+    Returns (W, Z, info)."""
+    torch = _torch()
+    d = _dev_f64(d, device)
+    e = _dev_f64(e, device)
+    n = d.numel()
+    iu = n if iu is None else iu
+    m = iu - il + 1
+    W = torch.empty(max(m, 1), dtype=torch.float64, device=d.device)
+    Z = torch.empty((max(m, 1), n), dtype=torch.float64, device=d.device)
+    wg = _dev_f64(W_given, device) if W_given is not None else None
+    need = tridiag_eigvecs_workspace_bytes(n, il, iu)
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=d.device)
+    base = ws.data_ptr()
+    pad = (-base) % 256
+    if info is None:
+        info = torch.zeros(m + 1, dtype=torch.int32, device=d.device)
+    o = _opts(**opts)
+    rc = lib().tridiag_eigvecs_ex(_vp(d.data_ptr()), _vp(e.data_ptr() if e.numel() else 0), n, il,
+                                  iu, _vp(wg.data_ptr() if wg is not None else 0),
+                                  _vp(W.data_ptr()), _vp(Z.data_ptr()), n, ctypes.byref(o),
+                                  _vp(base + pad), ws.numel() - pad, _vp(info.data_ptr()),
+                                  _stream_ptr(stream))
+    _check("tridiag_eigvecs_ex", rc)
+    return W[:m], Z[:m], info
+
+
+def tridiag_eigvecs_batched(problems, stream=None, device="cuda", **opts):
+    """problems: list of (d, e) or (d, e, il, iu) (numpy or tensors).
+    Returns a list of (W, Z) per problem (Z row j = eigenvector of W[j])."""
+    torch = _torch()
+    B = len(problems)
+    ns, ils, ius = [], [], []
+    ds, es = [], []
+    for p in problems:
+        d, e = p[0], p[1]
+        n = len(d)
+        il, iu = (p[2], p[3]) if len(p) >= 4 else (1, n)
+        ns.append(n)
+        ils.append(il)
+        ius.append(iu)
+        ds.append(_host_f64(d))
+        es.append(_host_f64(e))
+    off = np.zeros(B + 1, dtype=np.int64)
+    off[1:] = np.cumsum(ns)
+    ms = np.array([iu - il + 1 for il, iu in zip(ils, ius)], dtype=np.int64)
+    woff = np.zeros(B, dtype=np.int64)
+    woff[1:] = np.cumsum(ms)[:-1]
+    zsz = ms * np.array(ns, dtype=np.int64)
+    zoff = np.zeros(B, dtype=np.int64)
+    zoff[1:] = np.cumsum(zsz)[:-1]
+    d_all = _dev_f64(np.concatenate(ds), device)
+    e_cat = np.concatenate([x for x in es if len(x)]) if any(len(x) for x in es) else np.zeros(1)
+    e_all = _dev_f64(e_cat, device)
+    W_all = torch.empty(int(ms.sum()), dtype=torch.float64, device=d_all.device)
+    Z_all = torch.empty(int(zsz.sum()), dtype=torch.float64, device=d_all.device)
+    il_a = np.asarray(ils, dtype=np.int32)
+    iu_a = np.asarray(ius, dtype=np.int32)
+    o = _opts(**opts)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    rc = lib().tridiag_eigvecs_batched(_vp(d_all.data_ptr()), _vp(e_all.data_ptr()),
+                                       off.ctypes.data_as(i64p), il_a.ctypes.data_as(ip),
+                                       iu_a.ctypes.data_as(ip), _vp(W_all.data_ptr()),
+                                       woff.ctypes.data_as(i64p), _vp(Z_all.data_ptr()),
+                                       zoff.ctypes.data_as(i64p), B, ctypes.byref(o),
+                                       _stream_ptr(stream))
+    _check("tridiag_eigvecs_batched", rc)
+    out = []
+    for b in range(B):
+        m, n = int(ms[b]), ns[b]
+        W = W_all[woff[b]: woff[b] + m]
+        Z = Z_all[zoff[b]: zoff[b] + m * n].view(m, n)
+        out.append((W, Z))
+    return out

@@ -1,0 +1,576 @@
+// Host side of the tridiagonal eigenvector library: argument checks,
+// workspace layout, cluster-chain planning and the C-ABI entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "../../include/tridiag_eigvecs.h"
+#include "te_internal.h"
+
+namespace te {
+namespace {
+
+thread_local int g_last_hip = 0;
+
+inline int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return TE_ERR_HIP;
+}
+
+#define TE_CHECK(call)                          \
+  do {                                          \
+    hipError_t _e = (call);                     \
+    if (_e != hipSuccess) return hip_fail(_e);  \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// A cluster goes to the cooperative kernel when its Y block (n x size doubles)
+// exceeds this many entries; smaller chains run one per workgroup.
+constexpr size_t kLargeEntries = (size_t)1 << 20;
+
+struct Resolved {
+  int iters;
+  uint64_t seed;
+  double rtol;
+  int coop_wgs;
+};
+
+Resolved resolve(const te_opts *o) {
+  Resolved r{TE_DEFAULT_ITERS, TE_DEFAULT_SEED, 1e-3, 0};
+  if (o) {
+    if (o->iters > 0) r.iters = o->iters;
+    if (o->seed) r.seed = o->seed;
+    if (o->cluster_rtol > 0.0) r.rtol = o->cluster_rtol;
+    if (o->coop_wgs > 0) r.coop_wgs = o->coop_wgs;
+  }
+  return r;
+}
+
+struct DeviceLimits {
+  int device = -1;
+  int coop = 0;   // co-resident chain workgroups (cooperative kernel)
+  int small = 0;  // resident workgroups of the small-chain kernel
+};
+
+DeviceLimits limits() {
+  static std::mutex mu;
+  static DeviceLimits cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DeviceLimits{};
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev < 0 || dev >= 64) return DeviceLimits{};
+  if (cache[dev].device != dev) {
+    DeviceLimits L;
+    L.device = dev;
+    L.coop = coop_max_wgs(dev);
+    L.small = small_max_wgs(dev);
+    cache[dev] = L;
+  }
+  return cache[dev];
+}
+
+// Per-problem sizes of the workspace pieces (bytes, each aligned).
+struct ProbLayout {
+  size_t e2, nrm, pos, cls, clz, ncl, V, Ll, U1, U2, U3, Sw, Y, T, prm, info;
+  size_t total() const {
+    return e2 + nrm + pos + cls + clz + ncl + V + Ll + U1 + U2 + U3 + Sw + Y + T + prm + info;
+  }
+};
+
+ProbLayout prob_layout(int n, int m) {
+  ProbLayout L;
+  const size_t nm = (size_t)n * (size_t)m;
+  L.e2 = align_up(sizeof(double) * (size_t)std::max(n - 1, 1));
+  L.nrm = align_up(sizeof(double) * (size_t)m);
+  L.pos = align_up(sizeof(int) * (size_t)m);
+  L.cls = align_up(sizeof(int) * (size_t)m);
+  L.clz = align_up(sizeof(int) * (size_t)m);
+  L.ncl = align_up(sizeof(int));
+  L.V = align_up(sizeof(double) * nm);
+  L.Ll = L.V;
+  L.U1 = L.V;
+  L.U2 = L.V;
+  L.U3 = L.V;
+  L.Sw = align_up(nm);
+  L.Y = L.V;
+  L.T = align_up(sizeof(double) * (size_t)m * (size_t)m);
+  L.prm = align_up(sizeof(Params));
+  L.info = align_up(sizeof(int) * ((size_t)m + 1));
+  return L;
+}
+
+// Bump allocator over a caller- or library-owned device block.
+struct Carve {
+  char *base;
+  size_t off, cap;
+  template <class T>
+  T *take(size_t bytes) {
+    T *p = reinterpret_cast<T *>(base + off);
+    off += align_up(bytes);
+    return p;
+  }
+};
+
+struct ProblemDesc {
+  const double *d, *e;
+  int n, il, iu;
+  double *W, *Z;
+  int ldz;
+};
+
+// Everything one call needs after the problems are described.
+struct Run {
+  std::vector<Prob> hp;             // host copies of the problem descriptors
+  std::vector<int64_t> loff;        // lane offsets (nprob + 1)
+  Prob *dprobs = nullptr;
+  int64_t *dloff = nullptr;
+  int nmax = 0, mmax = 0;
+  int64_t mtotal = 0;
+};
+
+size_t fixed_bytes(int nprob) {
+  return align_up(sizeof(Prob) * (size_t)nprob) + align_up(sizeof(int64_t) * ((size_t)nprob + 1));
+}
+
+size_t chain_bytes(int nmax, int mmax, int nslots, int coop_wgs, int nitems) {
+  size_t b = 0;
+  b += align_up(sizeof(double) * chain_scratch_doubles(nmax, mmax, std::max(coop_wgs, 1)) *
+                (size_t)std::max(nslots, 1));
+  b += align_up(sizeof(ChainItem) * (size_t)std::max(nitems, 1));
+  b += align_up(sizeof(Group) * (size_t)std::max(coop_wgs, 1));
+  b += align_up(sizeof(int) * (size_t)std::max(coop_wgs, 1));      // wg_group
+  b += align_up(sizeof(unsigned) * (size_t)std::max(coop_wgs, 1)); // barriers
+  b += align_up(sizeof(int) * 2);                                  // abort flag, counter
+  return b;
+}
+
+// Split the large clusters into cooperative groups: sizes proportional to the
+// chain cost (size^2 * n), at least one workgroup each; with more clusters than
+// workgroups, single-workgroup groups take clusters longest-first.
+void plan_groups(const std::vector<ChainItem> &items, const std::vector<double> &cost, int nwg,
+                 std::vector<Group> &groups, std::vector<int> &wg_group,
+                 std::vector<ChainItem> &ordered) {
+  groups.clear();
+  ordered.clear();
+  wg_group.assign((size_t)nwg, -1);
+  const int K = (int)items.size();
+  if (K == 0 || nwg <= 0) return;
+  std::vector<int> idx(K);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  if (K <= nwg) {
+    double tot = 0.0;
+    for (int k = 0; k < K; k++) tot += cost[k];
+    std::vector<int> g(K, 1);
+    int used = K;
+    // hand out the remaining workgroups by largest remaining cost per WG
+    std::vector<double> share(K);
+    for (int a = 0; a < K; a++) share[a] = cost[idx[a]] / tot * nwg;
+    for (int a = 0; a < K; a++) {
+      const int want = std::max(1, (int)share[a]);
+      const int extra = std::min(want - 1, nwg - used);
+      g[a] += std::max(extra, 0);
+      used += std::max(extra, 0);
+    }
+    while (used < nwg) {  // leftovers to the most loaded per workgroup
+      int best = 0;
+      for (int a = 1; a < K; a++)
+        if (cost[idx[a]] / g[a] > cost[idx[best]] / g[best]) best = a;
+      g[best]++;
+      used++;
+    }
+    int wg0 = 0;
+    for (int a = 0; a < K; a++) {
+      Group G{wg0, g[a], (int)ordered.size(), 1};
+      ordered.push_back(items[idx[a]]);
+      for (int w = 0; w < g[a]; w++) wg_group[wg0 + w] = (int)groups.size();
+      groups.push_back(G);
+      wg0 += g[a];
+    }
+  } else {
+    std::vector<std::vector<int>> lists(nwg);
+    std::vector<double> load(nwg, 0.0);
+    for (int a = 0; a < K; a++) {
+      int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      lists[best].push_back(idx[a]);
+      load[best] += cost[idx[a]];
+    }
+    for (int w = 0; w < nwg; w++) {
+      Group G{w, 1, (int)ordered.size(), (int)lists[w].size()};
+      for (int k : lists[w]) ordered.push_back(items[k]);
+      wg_group[w] = (int)groups.size();
+      groups.push_back(G);
+    }
+  }
+}
+
+// The whole method for a set of problems.  ws may be null (library-owned
+// workspace via hipMallocAsync).  W_given: device array of mtotal eigenvalues
+// or null.
+int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, const Resolved &opt,
+                   void *ws, size_t ws_bytes, int *info, hipStream_t stream) {
+  const int nprob = (int)pd.size();
+  DeviceLimits lim = limits();
+  if (lim.device < 0 || lim.coop <= 0 || lim.small <= 0) return TE_ERR_NO_DEVICE;
+
+  Run R;
+  R.hp.resize(nprob);
+  R.loff.resize(nprob + 1);
+  R.loff[0] = 0;
+  size_t per_prob = 0;
+  for (int b = 0; b < nprob; b++) {
+    const int m = pd[b].iu - pd[b].il + 1;
+    R.nmax = std::max(R.nmax, pd[b].n);
+    R.mmax = std::max(R.mmax, m);
+    R.loff[b + 1] = R.loff[b] + m;
+    per_prob += prob_layout(pd[b].n, m).total();
+  }
+  R.mtotal = R.loff[nprob];
+
+  // Workspace: fixed part + problems; the chain part is sized after planning.
+  const size_t first_bytes = fixed_bytes(nprob) + per_prob;
+  bool own = (ws == nullptr);
+  char *base = static_cast<char *>(ws);
+  if (own) {
+    TE_CHECK(hipMallocAsync((void **)&base, first_bytes, stream));
+  } else if (ws_bytes < first_bytes) {
+    return TE_ERR_WORKSPACE;
+  }
+  Carve cv{base, 0, own ? first_bytes : ws_bytes};
+  R.dprobs = cv.take<Prob>(sizeof(Prob) * nprob);
+  R.dloff = cv.take<int64_t>(sizeof(int64_t) * (nprob + 1));
+  std::vector<Params> hprm(nprob);
+  for (int b = 0; b < nprob; b++) {
+    const int n = pd[b].n, m = pd[b].iu - pd[b].il + 1;
+    const size_t nm = (size_t)n * m;
+    Prob &P = R.hp[b];
+    std::memset(&P, 0, sizeof(P));
+    P.d = pd[b].d;
+    P.e = pd[b].e;
+    P.n = n;
+    P.m = m;
+    P.ldz = pd[b].ldz;
+    P.kbase = pd[b].il;
+    P.W = pd[b].W;
+    P.Z = pd[b].Z;
+    P.e2 = cv.take<double>(sizeof(double) * std::max(n - 1, 1));
+    P.nrm = cv.take<double>(sizeof(double) * m);
+    P.pos = cv.take<int>(sizeof(int) * m);
+    P.cl_start = cv.take<int>(sizeof(int) * m);
+    P.cl_size = cv.take<int>(sizeof(int) * m);
+    P.ncl = cv.take<int>(sizeof(int));
+    P.V = cv.take<double>(sizeof(double) * nm);
+    P.Ll = cv.take<double>(sizeof(double) * nm);
+    P.Lu1i = cv.take<double>(sizeof(double) * nm);
+    P.Lu2 = cv.take<double>(sizeof(double) * nm);
+    P.Lu3 = cv.take<double>(sizeof(double) * nm);
+    P.Lsw = cv.take<unsigned char>(nm);
+    P.Y = cv.take<double>(sizeof(double) * nm);
+    P.T = cv.take<double>(sizeof(double) * (size_t)m * m);
+    P.prm = cv.take<Params>(sizeof(Params));
+    int *pinfo = cv.take<int>(sizeof(int) * ((size_t)m + 1));
+    P.info = (info && nprob == 1) ? info : pinfo;
+    std::memset(&hprm[b], 0, sizeof(Params));
+    hprm[b].rtol = opt.rtol;
+  }
+  TE_CHECK(hipMemcpyAsync(R.dprobs, R.hp.data(), sizeof(Prob) * nprob, hipMemcpyHostToDevice,
+                          stream));
+  TE_CHECK(hipMemcpyAsync(R.dloff, R.loff.data(), sizeof(int64_t) * (nprob + 1),
+                          hipMemcpyHostToDevice, stream));
+  for (int b = 0; b < nprob; b++) {
+    TE_CHECK(hipMemcpyAsync(R.hp[b].prm, &hprm[b], sizeof(Params), hipMemcpyHostToDevice, stream));
+    TE_CHECK(launch_fill_i32(R.hp[b].info, (size_t)R.hp[b].m + 1, 0, stream));
+  }
+
+  // a1-a6
+  TE_CHECK(launch_setup(R.dprobs, nprob, stream));
+  if (W_given) TE_CHECK(launch_copy_w(R.dprobs, nprob, R.dloff, R.mtotal, W_given, stream));
+  else TE_CHECK(launch_bisect(R.dprobs, nprob, R.dloff, R.mtotal, stream));
+  TE_CHECK(launch_cluster(R.dprobs, nprob, stream));
+  TE_CHECK(launch_invit(R.dprobs, nprob, R.dloff, R.mtotal, opt.iters, opt.seed, stream));
+  TE_CHECK(launch_transpose(R.dprobs, nprob, R.nmax, R.mmax, stream));
+
+  // Cluster tables back to the host for the chain plan.
+  std::vector<int> ncl(nprob);
+  std::vector<std::vector<int>> cst(nprob), csz(nprob);
+  for (int b = 0; b < nprob; b++)
+    TE_CHECK(hipMemcpyAsync(&ncl[b], R.hp[b].ncl, sizeof(int), hipMemcpyDeviceToHost, stream));
+  TE_CHECK(hipStreamSynchronize(stream));
+  for (int b = 0; b < nprob; b++) {
+    cst[b].resize(std::max(ncl[b], 1));
+    csz[b].resize(std::max(ncl[b], 1));
+    if (ncl[b] > 0) {
+      TE_CHECK(hipMemcpyAsync(cst[b].data(), R.hp[b].cl_start, sizeof(int) * ncl[b],
+                              hipMemcpyDeviceToHost, stream));
+      TE_CHECK(hipMemcpyAsync(csz[b].data(), R.hp[b].cl_size, sizeof(int) * ncl[b],
+                              hipMemcpyDeviceToHost, stream));
+    }
+  }
+  TE_CHECK(hipStreamSynchronize(stream));
+
+  std::vector<ChainItem> small_items, large_items;
+  std::vector<double> small_cost, large_cost;
+  for (int b = 0; b < nprob; b++) {
+    for (int c = 0; c < ncl[b]; c++) {
+      if (csz[b][c] < 2) continue;
+      ChainItem it{b, cst[b][c], csz[b][c], 0};
+      const double cost = (double)csz[b][c] * csz[b][c] * R.hp[b].n;
+      if ((size_t)csz[b][c] * (size_t)R.hp[b].n >= kLargeEntries) {
+        large_items.push_back(it);
+        large_cost.push_back(cost);
+      } else {
+        small_items.push_back(it);
+        small_cost.push_back(cost);
+      }
+    }
+  }
+  {  // small items longest first
+    std::vector<int> idx(small_items.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int a, int b) { return small_cost[a] > small_cost[b]; });
+    std::vector<ChainItem> s2;
+    for (int k : idx) s2.push_back(small_items[k]);
+    small_items.swap(s2);
+  }
+  int coop_nwg = std::min(lim.coop, opt.coop_wgs > 0 ? opt.coop_wgs : lim.coop);
+  std::vector<Group> groups;
+  std::vector<int> wg_group;
+  std::vector<ChainItem> large_ordered;
+  plan_groups(large_items, large_cost, coop_nwg, groups, wg_group, large_ordered);
+  const int small_nwg = std::min((int)small_items.size(), lim.small);
+  const int nslots = std::max(small_nwg, (int)groups.size());
+  const int nitems = (int)(small_items.size() + large_ordered.size());
+
+  char *cbase = nullptr;
+  const size_t cbytes = chain_bytes(R.nmax, R.mmax, nslots, coop_nwg, nitems);
+  if (own) {
+    TE_CHECK(hipMallocAsync((void **)&cbase, cbytes, stream));
+  } else {
+    if (cv.off + cbytes > cv.cap) return TE_ERR_WORKSPACE;
+    cbase = base + cv.off;
+  }
+  Carve cc{cbase, 0, cbytes};
+  ChainScratch scr;
+  scr.stride = chain_scratch_doubles(R.nmax, R.mmax, std::max(coop_nwg, 1));
+  scr.base = cc.take<double>(sizeof(double) * scr.stride * std::max(nslots, 1));
+  ChainItem *ditems = cc.take<ChainItem>(sizeof(ChainItem) * std::max(nitems, 1));
+  Group *dgroups = cc.take<Group>(sizeof(Group) * std::max(coop_nwg, 1));
+  int *dwg = cc.take<int>(sizeof(int) * std::max(coop_nwg, 1));
+  unsigned *dbars = cc.take<unsigned>(sizeof(unsigned) * std::max(coop_nwg, 1));
+  int *dflags = cc.take<int>(sizeof(int) * 2);   // [0] abort, [1] work counter
+
+  std::vector<ChainItem> all_items(small_items);
+  all_items.insert(all_items.end(), large_ordered.begin(), large_ordered.end());
+  if (nitems > 0)
+    TE_CHECK(hipMemcpyAsync(ditems, all_items.data(), sizeof(ChainItem) * nitems,
+                            hipMemcpyHostToDevice, stream));
+  TE_CHECK(launch_fill_i32(dflags, 2, 0, stream));
+  if (small_nwg > 0)
+    TE_CHECK(launch_chain_small(R.dprobs, ditems, (int)small_items.size(), dflags + 1, scr,
+                                small_nwg, opt.iters, stream));
+  if (!groups.empty()) {
+    std::vector<Group> g2(groups);
+    for (auto &G : g2) G.it0 += (int)small_items.size();
+    TE_CHECK(hipMemcpyAsync(dgroups, g2.data(), sizeof(Group) * g2.size(), hipMemcpyHostToDevice,
+                            stream));
+    TE_CHECK(hipMemcpyAsync(dwg, wg_group.data(), sizeof(int) * coop_nwg, hipMemcpyHostToDevice,
+                            stream));
+    TE_CHECK(launch_fill_i32((int *)dbars, (size_t)coop_nwg, 0, stream));
+    TE_CHECK(launch_chain_coop(R.dprobs, ditems, dgroups, dwg, dbars, dflags, scr, coop_nwg,
+                               opt.iters, stream));
+  }
+  TE_CHECK(launch_finalize(R.dprobs, nprob, R.dloff, R.mtotal, stream));
+  int abort_flag = 0;
+  TE_CHECK(hipMemcpyAsync(&abort_flag, dflags, sizeof(int), hipMemcpyDeviceToHost, stream));
+  TE_CHECK(hipStreamSynchronize(stream));
+  if (own) {
+    TE_CHECK(hipFreeAsync(cbase, stream));
+    TE_CHECK(hipFreeAsync(base, stream));
+    TE_CHECK(hipStreamSynchronize(stream));
+  }
+  return abort_flag ? TE_ERR_KERNEL : 0;
+}
+
+}  // namespace
+}  // namespace te
+
+using namespace te;
+
+extern "C" {
+
+int te_last_hip_error(void) { return g_last_hip; }
+
+int tridiag_eigvecs(const double *d, const double *e, int n, int il, int iu, double *W, double *Z,
+                    int ldz, hipStream_t stream) {
+  if (!d) return -1;
+  if (!e && n > 1) return -2;
+  if (n < 1) return -3;
+  if (il < 1 || il > n) return -4;
+  if (iu < il || iu > n) return -5;
+  if (!W) return -6;
+  if (!Z) return -7;
+  if (ldz < n) return -8;
+  std::vector<ProblemDesc> pd{{d, e, n, il, iu, W, Z, ldz}};
+  return solve_problems(pd, nullptr, resolve(nullptr), nullptr, 0, nullptr, stream);
+}
+
+int tridiag_eigvecs_given_w(const double *d, const double *e, int n, int m, const double *W,
+                            double *Z, int ldz, hipStream_t stream) {
+  if (!d) return -1;
+  if (!e && n > 1) return -2;
+  if (n < 1) return -3;
+  if (m < 1 || m > n) return -4;
+  if (!W) return -5;
+  if (!Z) return -6;
+  if (ldz < n) return -7;
+  // W is both the input and (copied onto itself) the output eigenvalue array.
+  std::vector<ProblemDesc> pd{{d, e, n, 1, m, const_cast<double *>(W), Z, ldz}};
+  double *Wtmp = nullptr;
+  hipError_t he = hipMallocAsync((void **)&Wtmp, sizeof(double) * m, stream);
+  if (he != hipSuccess) return hip_fail(he);
+  he = hipMemcpyAsync(Wtmp, W, sizeof(double) * m, hipMemcpyDeviceToDevice, stream);
+  if (he != hipSuccess) return hip_fail(he);
+  const int rc = solve_problems(pd, Wtmp, resolve(nullptr), nullptr, 0, nullptr, stream);
+  he = hipFreeAsync(Wtmp, stream);
+  if (rc == 0 && he != hipSuccess) return hip_fail(he);
+  return rc;
+}
+
+size_t tridiag_eigvecs_workspace_bytes(int n, int il, int iu) {
+  if (n < 1 || il < 1 || iu < il || iu > n) return 0;
+  const int m = iu - il + 1;
+  DeviceLimits lim = limits();
+  const int coop = lim.coop > 0 ? lim.coop : 4096;
+  const int small = lim.small > 0 ? lim.small : 4096;
+  return fixed_bytes(1) + prob_layout(n, m).total() +
+         chain_bytes(n, m, std::max(coop, small), coop, m);
+}
+
+int tridiag_eigvecs_ex(const double *d, const double *e, int n, int il, int iu,
+                       const double *W_given, double *W, double *Z, int ldz, const te_opts *opt,
+                       void *ws, size_t ws_bytes, int *info, hipStream_t stream) {
+  if (!d) return -1;
+  if (!e && n > 1) return -2;
+  if (n < 1) return -3;
+  if (il < 1 || il > n) return -4;
+  if (iu < il || iu > n) return -5;
+  if (!W) return -7;
+  if (!Z) return -8;
+  if (ldz < n) return -9;
+  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0)) return -10;
+  if (!ws) return -11;
+  if (ws_bytes < tridiag_eigvecs_workspace_bytes(n, il, iu)) return -12;
+  if (((uintptr_t)ws) % kAlign) return -11;
+  std::vector<ProblemDesc> pd{{d, e, n, il, iu, W, Z, ldz}};
+  return solve_problems(pd, W_given, resolve(opt), ws, ws_bytes, info, stream);
+}
+
+int tridiag_eigvals(const double *d, const double *e, int n, int il, int iu, double *W,
+                    hipStream_t stream) {
+  if (!d) return -1;
+  if (!e && n > 1) return -2;
+  if (n < 1) return -3;
+  if (il < 1 || il > n) return -4;
+  if (iu < il || iu > n) return -5;
+  if (!W) return -6;
+  if (limits().device < 0) return TE_ERR_NO_DEVICE;
+  const int m = iu - il + 1;
+  const size_t bytes = fixed_bytes(1) + align_up(sizeof(double) * std::max(n - 1, 1)) +
+                       align_up(sizeof(Params));
+  char *base = nullptr;
+  TE_CHECK(hipMallocAsync((void **)&base, bytes, stream));
+  Carve cv{base, 0, bytes};
+  Prob *dp = cv.take<Prob>(sizeof(Prob));
+  int64_t *dloff = cv.take<int64_t>(sizeof(int64_t) * 2);
+  Prob P;
+  std::memset(&P, 0, sizeof(P));
+  P.d = d; P.e = e; P.n = n; P.m = m; P.kbase = il; P.W = W; P.ldz = n;
+  P.e2 = cv.take<double>(sizeof(double) * std::max(n - 1, 1));
+  P.prm = cv.take<Params>(sizeof(Params));
+  Params hp;
+  std::memset(&hp, 0, sizeof(hp));
+  hp.rtol = 1e-3;
+  const int64_t loff[2] = {0, m};
+  TE_CHECK(hipMemcpyAsync(dp, &P, sizeof(P), hipMemcpyHostToDevice, stream));
+  TE_CHECK(hipMemcpyAsync(dloff, loff, sizeof(loff), hipMemcpyHostToDevice, stream));
+  TE_CHECK(hipMemcpyAsync(P.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, stream));
+  TE_CHECK(launch_setup(dp, 1, stream));
+  TE_CHECK(launch_bisect(dp, 1, dloff, m, stream));
+  TE_CHECK(hipFreeAsync(base, stream));
+  TE_CHECK(hipStreamSynchronize(stream));
+  return 0;
+}
+
+int tridiag_clusters(const double *W, int m, double tol, int *start, int *size, int *ncl,
+                     hipStream_t stream) {
+  if (!W) return -1;
+  if (m < 1) return -2;
+  if (!(tol >= 0.0)) return -3;
+  if (!start) return -4;
+  if (!size) return -5;
+  if (!ncl) return -6;
+  if (limits().device < 0) return TE_ERR_NO_DEVICE;
+  const size_t bytes = fixed_bytes(1) + align_up(sizeof(Params)) + align_up(sizeof(int) * m);
+  char *base = nullptr;
+  TE_CHECK(hipMallocAsync((void **)&base, bytes, stream));
+  Carve cv{base, 0, bytes};
+  Prob *dp = cv.take<Prob>(sizeof(Prob));
+  Prob P;
+  std::memset(&P, 0, sizeof(P));
+  P.m = m; P.W = const_cast<double *>(W); P.cl_start = start; P.cl_size = size; P.ncl = ncl;
+  P.prm = cv.take<Params>(sizeof(Params));
+  P.pos = cv.take<int>(sizeof(int) * m);
+  Params hp;
+  std::memset(&hp, 0, sizeof(hp));
+  hp.tol = tol;
+  TE_CHECK(hipMemcpyAsync(dp, &P, sizeof(P), hipMemcpyHostToDevice, stream));
+  TE_CHECK(hipMemcpyAsync(P.prm, &hp, sizeof(hp), hipMemcpyHostToDevice, stream));
+  TE_CHECK(launch_cluster(dp, 1, stream));
+  TE_CHECK(hipFreeAsync(base, stream));
+  TE_CHECK(hipStreamSynchronize(stream));
+  return 0;
+}
+
+int tridiag_eigvecs_batched(const double *d_all, const double *e_all, const int64_t *off,
+                            const int *il, const int *iu, double *W_all, const int64_t *woff,
+                            double *Z_all, const int64_t *zoff, int B, const te_opts *opt,
+                            hipStream_t stream) {
+  if (!d_all) return -1;
+  if (!off) return -3;
+  if (!il) return -4;
+  if (!iu) return -5;
+  if (!W_all) return -6;
+  if (!woff) return -7;
+  if (!Z_all) return -8;
+  if (!zoff) return -9;
+  if (B < 1) return -10;
+  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0)) return -11;
+  std::vector<ProblemDesc> pd(B);
+  bool any_e = false;
+  for (int b = 0; b < B; b++) {
+    const int64_t nb = off[b + 1] - off[b];
+    if (nb < 1 || nb > (1 << 30)) return -3;
+    if (il[b] < 1 || il[b] > nb) return -4;
+    if (iu[b] < il[b] || iu[b] > nb) return -5;
+    if (nb > 1) any_e = true;
+    pd[b].d = d_all + off[b];
+    pd[b].e = e_all ? e_all + (off[b] - b) : nullptr;
+    pd[b].n = (int)nb;
+    pd[b].il = il[b];
+    pd[b].iu = iu[b];
+    pd[b].W = W_all + woff[b];
+    pd[b].Z = Z_all + zoff[b];
+    pd[b].ldz = (int)nb;
+  }
+  if (any_e && !e_all) return -2;
+  return solve_problems(pd, nullptr, resolve(opt), nullptr, 0, nullptr, stream);
+}
+
+}  // extern "C"

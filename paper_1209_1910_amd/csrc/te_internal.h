@@ -1,0 +1,101 @@
+// Internal declarations shared by the kernels (te_kernels.hip) and the host
+// orchestration (te_api.hip) of the tridiagonal eigenvector library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace te {
+
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kChainThreads = 256;   // 4 waves per chain workgroup
+constexpr int kChainWaves = kChainThreads / kWave;
+
+// Per-problem scalars from the setup pass.
+struct Params {
+  double norm1;   // ||T||_1
+  double tol;     // cluster gap threshold, rtol * ||T||_1
+  double pivmin;  // Sturm-count pivot floor
+  double pivthr;  // LU pivot floor, eps * ||T||_1
+  double gl, gu;  // widened bisection bracket
+  double tnorm;   // max(|gl|, |gu|) of the unwidened Gershgorin interval
+  double rtol;    // cluster gap as a multiple of ||T||_1 (input)
+};
+
+// One problem as seen by the kernels.  All arrays are device memory.
+// Per-eigenvalue arrays of n entries (LU factors of T - W[j] I and the
+// iterate) are stored interleaved: entry (row i, eigenvalue j) at i * m + j,
+// so that one lane per eigenvalue reads and writes coalesced.
+struct Prob {
+  const double *d;      // n
+  const double *e;      // n - 1
+  double *e2;           // n - 1: e_i^2
+  Params *prm;          // 1
+  double *W;            // m eigenvalues (ascending)
+  double *Z;            // eigenvectors, column-major, ld ldz
+  double *V;            // n * m iterate storage, interleaved
+  double *Ll;           // n * m multipliers l
+  double *Lu1i;         // n * m 1 / u1
+  double *Lu2;          // n * m u2 / u1
+  double *Lu3;          // n * m u3 / u1
+  unsigned char *Lsw;   // n * m row-swap flags
+  double *nrm;          // m: 2-norm of each final iterate of the parallel solve
+  int *pos;             // m: position of eigenvalue j in its cluster
+  int *cl_start;        // m: cluster starts (first *ncl valid)
+  int *cl_size;         // m
+  int *ncl;             // 1
+  double *Y;            // n * m: compact-WY Y, cluster column l at (start + l) * n
+  double *T;            // m * m: compact-WY T, column-major ld m (diagonal blocks)
+  int *info;            // 1 + m (may be null)
+  int n, m, ldz;
+  int kbase;            // global 1-based index of W[0] (start-vector key)
+};
+
+// A cluster chain work item: cluster [start, start + size) of problem prob.
+struct ChainItem {
+  int prob;
+  int start;
+  int size;
+  int pad;
+};
+
+// Cooperative-kernel group: WGs [wg0, wg0 + nwg) run items [it0, it0 + nit).
+struct Group {
+  int wg0, nwg;
+  int it0, nit;
+};
+
+// Chain scratch: one slot of `stride` doubles per small-kernel workgroup or
+// per cooperative group.
+struct ChainScratch {
+  double *base;
+  size_t stride;
+};
+
+size_t chain_scratch_doubles(int nmax, int mmax, int nwg_in_group);
+
+// Launch helpers (te_kernels.hip).  Multi-problem kernels map a flat lane
+// index t to (problem b, index j) through loff (nprob + 1 prefix offsets).
+hipError_t launch_setup(const Prob *probs, int nprob, hipStream_t s);
+hipError_t launch_bisect(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
+                         hipStream_t s);
+hipError_t launch_copy_w(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
+                         const double *Wsrc, hipStream_t s);
+hipError_t launch_cluster(const Prob *probs, int nprob, hipStream_t s);
+hipError_t launch_invit(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
+                        int iters, uint64_t seed, hipStream_t s);
+hipError_t launch_transpose(const Prob *probs, int nprob, int nmax, int mmax, hipStream_t s);
+hipError_t launch_chain_small(const Prob *probs, const ChainItem *items, int nitems,
+                              int *counter, ChainScratch scr, int nwg, int iters,
+                              hipStream_t s);
+hipError_t launch_chain_coop(const Prob *probs, const ChainItem *items, const Group *groups,
+                             const int *wg_group, unsigned *bars, int *abort_flag,
+                             ChainScratch scr, int nwg, int iters, hipStream_t s);
+hipError_t launch_finalize(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
+                           hipStream_t s);
+hipError_t launch_fill_i32(int *p, size_t n, int v, hipStream_t s);
+int coop_max_wgs(int device);
+int small_max_wgs(int device);
+
+}  // namespace te

@@ -1,0 +1,1007 @@
+// HIP kernels (gfx950, FP64) for inverse iteration with compact-WY
+// re-orthogonalization (Ishigami, Kimura, Nakamura, arXiv:1209.1910).
+//
+// Built with -ffp-contract=off: every multiply and add below is rounded on its
+// own unless written as fma(), so the Sturm counts, the bisection midpoints
+// and the LU factors follow the same IEEE operation sequence as a plain C
+// implementation of the same formulas.  Dot products use explicit fma().
+#include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
+#include <float.h>
+#include <math.h>
+
+#include "te_internal.h"
+
+namespace te {
+
+// ---------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+  // Fixed butterfly: every lane ends with the same, deterministic sum.
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+__device__ __forceinline__ int find_prob(const int64_t *loff, int nprob, int64_t t) {
+  int lo = 0, hi = nprob;  // loff[lo] <= t < loff[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (loff[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Sturm count: number of eigenvalues of T below sigma (negative pivots of the
+// LDL^T factorization of T - sigma I; pivots with |q| <= pivmin become -pivmin).
+// Reads d and e2 at uniform addresses across the wave.
+__device__ int sturm_count(int n, const double *__restrict__ d, const double *__restrict__ e2,
+                           double pivmin, double sigma) {
+  double q = d[0] - sigma;
+  if (fabs(q) <= pivmin) q = -pivmin;
+  int cnt = q < 0.0 ? 1 : 0;
+  for (int i = 1; i < n; i++) {
+    double t1 = d[i] - sigma;
+    double t2 = e2[i - 1] / q;
+    q = t1 - t2;
+    if (fabs(q) <= pivmin) q = -pivmin;
+    cnt += q < 0.0 ? 1 : 0;
+  }
+  return cnt;
+}
+
+// Entry i of the start vector of global eigenvalue index k: the
+// (((k << 32) | i) + 1)-th output of the SplitMix64 stream seeded with `seed`
+// (Steele, Lea, Flood 2014), mapped to [-1, 1).
+__device__ __forceinline__ double start_entry(uint64_t seed, uint64_t k, uint32_t i) {
+  uint64_t key = (k << 32) | (uint64_t)i;
+  uint64_t z = seed + (key + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  double u = (double)(z >> 11) * 0x1.0p-53;
+  return 2.0 * u - 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// a1: norm, tolerance, pivot floors and bisection bracket (one WG / problem)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_setup(const Prob *__restrict__ probs) {
+  const Prob P = probs[blockIdx.x];
+  const int n = P.n, tid = threadIdx.x;
+  __shared__ double s_red[4][4];
+  __shared__ double s_lohi[2];
+  __shared__ int s_cnt[2];
+  __shared__ int s_done;
+  double rmax = -INFINITY, lmin = INFINITY, hmax = -INFINITY, e2max = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    double r = fabs(P.d[i]);
+    double s = 0.0;
+    if (i > 0) { r = r + fabs(P.e[i - 1]); s = s + fabs(P.e[i - 1]); }
+    if (i < n - 1) {
+      r = r + fabs(P.e[i]);
+      s = s + fabs(P.e[i]);
+      double q = P.e[i] * P.e[i];
+      P.e2[i] = q;
+      e2max = fmax(e2max, q);
+    }
+    rmax = fmax(rmax, r);
+    lmin = fmin(lmin, P.d[i] - s);
+    hmax = fmax(hmax, P.d[i] + s);
+  }
+  rmax = wave_max(rmax); lmin = wave_min(lmin); hmax = wave_max(hmax); e2max = wave_max(e2max);
+  const int w = tid / kWave, lane = tid % kWave;
+  if (lane == 0) { s_red[0][w] = rmax; s_red[1][w] = lmin; s_red[2][w] = hmax; s_red[3][w] = e2max; }
+  __syncthreads();
+  const double norm1 = fmax(fmax(s_red[0][0], s_red[0][1]), fmax(s_red[0][2], s_red[0][3]));
+  const double gl = fmin(fmin(s_red[1][0], s_red[1][1]), fmin(s_red[1][2], s_red[1][3]));
+  const double gu = fmax(fmax(s_red[2][0], s_red[2][1]), fmax(s_red[2][2], s_red[2][3]));
+  const double me2 = fmax(fmax(s_red[3][0], s_red[3][1]), fmax(s_red[3][2], s_red[3][3]));
+  const double pivmin = DBL_MIN * (me2 > 1.0 ? me2 : 1.0);
+  const double tnorm = fabs(gl) > fabs(gu) ? fabs(gl) : fabs(gu);
+  __syncthreads();  // e2 visible to every wave
+  // Widen until count(lo) == 0 and count(hi) == n (the two counts run on two waves).
+  double wd = (2.0 * DBL_EPSILON * tnorm) * (double)n + 2.0 * pivmin;
+  if (tid == 0) s_done = 0;
+  for (int t = 0; t < 64; t++) {
+    const double lo = gl - wd, hi = gu + wd;
+    if (tid == 0) s_cnt[0] = sturm_count(n, P.d, P.e2, pivmin, lo);
+    if (tid == kWave) s_cnt[1] = sturm_count(n, P.d, P.e2, pivmin, hi);
+    __syncthreads();
+    if (tid == 0) {
+      s_lohi[0] = lo; s_lohi[1] = hi;
+      s_done = (s_cnt[0] == 0 && s_cnt[1] == n) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_done) break;
+    wd = 2.0 * wd;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    Params *p = P.prm;
+    const double rtol = p->rtol;
+    p->norm1 = norm1;
+    p->tol = rtol * norm1;
+    p->pivmin = pivmin;
+    p->pivthr = DBL_EPSILON * norm1;
+    p->gl = s_lohi[0];
+    p->gu = s_lohi[1];
+    p->tnorm = tnorm;
+  }
+}
+
+hipError_t launch_setup(const Prob *probs, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup, dim3(nprob), dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a2: Sturm-count bisection, one lane per requested eigenvalue
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_bisect(const Prob *__restrict__ probs, int nprob,
+                                                const int64_t *__restrict__ loff, int64_t nlanes) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nlanes) return;
+  const int b = find_prob(loff, nprob, t);
+  const Prob &P = probs[b];
+  const int j = (int)(t - loff[b]);
+  const Params prm = *P.prm;
+  const int k = P.kbase + j;
+  const double atol = 2.0 * DBL_EPSILON * prm.tnorm;
+  double lo = prm.gl, hi = prm.gu;
+  for (int it = 0; it < 128 && (hi - lo) > atol; it++) {
+    const double mid = lo + 0.5 * (hi - lo);
+    if (sturm_count(P.n, P.d, P.e2, prm.pivmin, mid) >= k) hi = mid;
+    else lo = mid;
+  }
+  P.W[j] = lo + 0.5 * (hi - lo);
+}
+
+hipError_t launch_bisect(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
+                         hipStream_t s) {
+  if (nlanes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bisect, dim3((unsigned)((nlanes + 255) / 256)), dim3(256), 0, s, probs,
+                     nprob, loff, nlanes);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_w(const Prob *__restrict__ probs, int nprob, const int64_t *__restrict__ loff,
+                         int64_t nlanes, const double *__restrict__ src) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nlanes) return;
+  const int b = find_prob(loff, nprob, t);
+  probs[b].W[t - loff[b]] = src[t];
+}
+
+hipError_t launch_copy_w(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
+                         const double *Wsrc, hipStream_t s) {
+  if (nlanes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_w, dim3((unsigned)((nlanes + 255) / 256)), dim3(256), 0, s, probs,
+                     nprob, loff, nlanes, Wsrc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a3: clusters by gap threshold (chain rule), one WG per problem
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_cluster(const Prob *__restrict__ probs) {
+  const Prob P = probs[blockIdx.x];
+  const int m = P.m, tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+  const double tol = P.prm->tol;
+  __shared__ int s_wcnt[4];
+  __shared__ int s_base;
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int base = 0; base < m; base += 256) {
+    const int j = base + tid;
+    const int flag = (j < m) && (j == 0 || (P.W[j] - P.W[j - 1]) > tol);
+    const unsigned long long bal = __ballot(flag);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wcnt[w] = __popcll(bal);
+    __syncthreads();
+    int off = s_base;
+    for (int q = 0; q < w; q++) off += s_wcnt[q];
+    if (flag) P.cl_start[off + before] = j;
+    __syncthreads();
+    if (tid == 0) s_base += s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+    __syncthreads();
+  }
+  const int ncl = s_base;
+  if (tid == 0) *P.ncl = ncl;
+  for (int c = tid; c < ncl; c += 256)
+    P.cl_size[c] = (c + 1 < ncl ? P.cl_start[c + 1] : m) - P.cl_start[c];
+  for (int j = tid; j < m; j += 256) {
+    int lo = 0, hi = ncl;  // cl_start[lo] <= j < cl_start[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (P.cl_start[mid] <= j) lo = mid; else hi = mid;
+    }
+    P.pos[j] = j - P.cl_start[lo];
+  }
+}
+
+hipError_t launch_cluster(const Prob *probs, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(k_cluster, dim3(nprob), dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a4-a6: start vectors, partial-pivoting LU of T - lambda_j I and the solves
+// of Eq. (1); one lane per eigenvalue, interleaved storage.
+//
+// Elimination step i keeps the active row (alpha at column i, beta at i+1).
+// Row i+1 of T - sigma I is (e_i, d_{i+1} - sigma, e_{i+1}).  Without a swap
+// the pivot row is the active row: U row i = (alpha, beta, 0), l = e_i/alpha.
+// With a swap (|e_i| > |alpha|) the pivot row is row i+1: U row i =
+// (e_i, d_{i+1} - sigma, e_{i+1}), l = alpha/e_i.  Pivots below pivthr in
+// magnitude become +-pivthr.  Stored per row: l, 1/u1, u2/u1, u3/u1, swap.
+//
+// The iterate lives in V (interleaved).  The forward sweep writes
+// y'_i = y_i / u1_i in place (slot i is overwritten only after it was read as
+// b_i); the back sweep x_i = y'_i - (u2/u1)_i x_{i+1} - (u3/u1)_i x_{i+2}
+// overwrites it again.  Singletons and first cluster members run all `iters`
+// iterations; later members run the first (chain-independent) one only.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_invit(const Prob *__restrict__ probs, int nprob,
+                                               const int64_t *__restrict__ loff, int64_t nlanes,
+                                               int iters, uint64_t seed) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nlanes) return;
+  const int b = find_prob(loff, nprob, t);
+  const Prob &P = probs[b];
+  const int j = (int)(t - loff[b]);
+  const int n = P.n;
+  const size_t m = (size_t)P.m;
+  const double *__restrict__ d = P.d;
+  const double *__restrict__ e = P.e;
+  double *__restrict__ V = P.V + j;
+  double *__restrict__ Ll = P.Ll + j;
+  double *__restrict__ U1 = P.Lu1i + j;
+  double *__restrict__ U2 = P.Lu2 + j;
+  double *__restrict__ U3 = P.Lu3 + j;
+  unsigned char *__restrict__ SW = P.Lsw + j;
+  const double sigma = P.W[j];
+  const double pivthr = P.prm->pivthr;
+  const int K = P.pos[j] == 0 ? iters : 1;
+  const uint64_t kglob = (uint64_t)(P.kbase + j);
+
+  double ss = 0.0;
+  for (int i = 0; i < n; i++) {
+    const double v = start_entry(seed, kglob, (uint32_t)i);
+    V[(size_t)i * m] = v;
+    ss = fma(v, v, ss);
+  }
+  for (int k = 1; k <= K; k++) {
+    const double rn = 1.0 / sqrt(ss);
+    double cur = V[0] * rn;
+    if (k == 1) {
+      double alpha = d[0] - sigma;
+      double beta = n > 1 ? e[0] : 0.0;
+      for (int i = 0; i < n - 1; i++) {
+        const double bi = e[i];
+        const double a1 = d[i + 1] - sigma;
+        const double b1 = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+        const double bn = V[(size_t)(i + 1) * m] * rn;
+        double piv, u2, u3, l, y;
+        unsigned char sw;
+        if (fabs(alpha) >= fabs(bi)) {
+          piv = alpha;
+          if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+          u2 = beta; u3 = 0.0; sw = 0;
+          l = bi / piv;
+          alpha = a1 - l * beta;
+          beta = b1;
+          y = cur;
+          cur = bn - l * cur;
+        } else {
+          piv = bi;
+          if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+          u2 = a1; u3 = b1; sw = 1;
+          l = alpha / piv;
+          alpha = beta - l * a1;
+          beta = -(l * b1);
+          y = bn;
+          cur = cur - l * bn;
+        }
+        const double inv = 1.0 / piv;
+        const size_t o = (size_t)i * m;
+        Ll[o] = l; U1[o] = inv; U2[o] = u2 * inv; U3[o] = u3 * inv; SW[o] = sw;
+        V[o] = y * inv;
+      }
+      double piv = alpha;
+      if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+      const double inv = 1.0 / piv;
+      const size_t o = (size_t)(n - 1) * m;
+      Ll[o] = 0.0; U1[o] = inv; U2[o] = 0.0; U3[o] = 0.0; SW[o] = 0;
+      V[o] = cur * inv;
+    } else {
+      for (int i = 0; i < n - 1; i++) {
+        const size_t o = (size_t)i * m;
+        const double bn = V[o + m] * rn;
+        const double l = Ll[o];
+        double y;
+        if (SW[o]) { y = bn; cur = cur - l * bn; }
+        else { y = cur; cur = bn - l * cur; }
+        V[o] = y * U1[o];
+      }
+      const size_t o = (size_t)(n - 1) * m;
+      V[o] = cur * U1[o];
+    }
+    // back substitution
+    ss = 0.0;
+    double x1 = 0.0, x2 = 0.0;
+    for (int i = n - 1; i >= 0; i--) {
+      const size_t o = (size_t)i * m;
+      const double x = fma(-U2[o], x1, fma(-U3[o], x2, V[o]));
+      V[o] = x;
+      ss = fma(x, x, ss);
+      x2 = x1;
+      x1 = x;
+    }
+  }
+  P.nrm[j] = sqrt(ss);
+}
+
+hipError_t launch_invit(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
+                        int iters, uint64_t seed, hipStream_t s) {
+  if (nlanes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_invit, dim3((unsigned)((nlanes + 255) / 256)), dim3(256), 0, s, probs,
+                     nprob, loff, nlanes, iters, seed);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// V (interleaved) -> Z (column-major).  Singletons and first cluster members
+// are normalized here (the first member's unit vector seeds Y_1, T_1); later
+// members keep the raw first-iteration solve, the input of their first
+// compact-WY step.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_transpose(const Prob *__restrict__ probs) {
+  const Prob &P = probs[blockIdx.z];
+  const int n = P.n, m = P.m;
+  const int j0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
+  if (j0 >= m || i0 >= n) return;
+  __shared__ double tile[64][65];
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+  for (int r = ty; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + tx;
+    if (i < n && j < m) tile[r][tx] = P.V[(size_t)i * m + j];
+  }
+  __syncthreads();
+  for (int c = ty; c < 64; c += 4) {
+    const int j = j0 + c, i = i0 + tx;
+    if (i < n && j < m) {
+      const double sc = P.pos[j] == 0 ? 1.0 / P.nrm[j] : 1.0;
+      P.Z[(size_t)j * P.ldz + i] = tile[tx][c] * sc;
+    }
+  }
+}
+
+hipError_t launch_transpose(const Prob *probs, int nprob, int nmax, int mmax, hipStream_t s) {
+  if (nprob <= 0 || nmax <= 0 || mmax <= 0) return hipSuccess;
+  dim3 grid((mmax + 63) / 64, (nmax + 63) / 64, nprob);
+  hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a7: the compact-WY chain of one cluster (Alg. 4 with section 3.3.2).
+//
+// A group of G workgroups (G = 1 for the small kernel) runs the members
+// c = 1..M-1 of the cluster in order; member c runs `iters` steps, each a
+// compact-WY orthogonalization of its current iterate v followed, except
+// after the last step, by the solve of Eq. (1).  Y (n x M, column l holds
+// y_{l}: zero above row l, never read there) and T (M x M upper triangular)
+// live in HBM; the phases of one step are separated by group barriers:
+//
+//  P1  x   = Y_c^T v                (L^T v_chk + Yhat^T v_hat, column dots)
+//  P2  x'  = T_c^T x                (column dots over the upper triangle)
+//  P3  u   = v_hat - Yhat_c x'      (rows c..n-1, row tiles) and ||u||^2
+//  P4  c_j = -sgn(u_c)||u||, t_j = 1/(c_j^2 - u_c c_j), y_hat = u with
+//      u_c - c_j at row c; s = Yhat_c^T y_hat (column dots); column c of Y
+//  P5  t_hat = -t_j T_c s and x'' = T_{c+1} r, r = row c of Y_{c+1}
+//      (one pass over T_c for both vectors); column c of T
+//  P6  q = Y_{c+1} x'' - e_c        (rows 0..n-1, row tiles)
+//  P7  v = (T - lambda I)^{-1} q/||q||  (rank-0 workgroup)
+//
+// The product in P5 uses T_{c+1}; the transposed factor printed for this
+// step in section 3.3.2 does not give orthonormal columns.
+// ---------------------------------------------------------------------------
+
+struct Ctx {
+  int rank, size;      // workgroup rank in the group, group size (WGs)
+  unsigned *bar;       // group barrier counter (unused when size == 1)
+  unsigned target;     // counter value that ends the next barrier
+  int *abort_flag;
+  int gw, nw;          // wave index in the group, waves in the group
+  int wave, lane;
+};
+
+constexpr unsigned long long kSpinLimit = 1ull << 22;  // ~seconds: only a broken run waits that long
+
+// Group barrier.  Returns false (for every thread of the WG) when the run was
+// aborted, so callers unwind; a barrier that times out sets the abort flag.
+__device__ bool grp_sync(Ctx &c) {
+  __syncthreads();
+  if (c.size == 1) return true;
+  __shared__ int s_ok;
+  c.target += (unsigned)c.size;
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __atomic_thread_fence(__ATOMIC_RELEASE);
+    __hip_atomic_fetch_add(c.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long spins = 0;
+    while (__hip_atomic_load(c.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < c.target) {
+      if (__hip_atomic_load(c.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > kSpinLimit) {
+        __hip_atomic_store(c.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// Scratch layout of one chain slot.
+struct Scr {
+  double *v, *q, *u, *P, *Q;       // n each
+  double *x, *xp, *s, *r, *xpp;    // mmax + 1 each
+  double *carry;                   // 2 (n / 64) + 8: chunk summaries, then carries
+  double *red;                     // nwg + 8
+};
+
+__host__ __device__ inline size_t scr_doubles(int nmax, int mmax, int nwg) {
+  return 5 * (size_t)nmax + 5 * ((size_t)mmax + 1) + (2 * ((size_t)nmax / 64) + 8) + (size_t)nwg + 8 + 64;
+}
+
+size_t chain_scratch_doubles(int nmax, int mmax, int nwg_in_group) {
+  return scr_doubles(nmax, mmax, nwg_in_group);
+}
+
+__device__ inline Scr make_scr(double *base, int nmax, int mmax) {
+  Scr S;
+  double *p = base;
+  S.v = p; p += nmax;
+  S.q = p; p += nmax;
+  S.u = p; p += nmax;
+  S.P = p; p += nmax;
+  S.Q = p; p += nmax;
+  S.x = p; p += mmax + 1;
+  S.xp = p; p += mmax + 1;
+  S.s = p; p += mmax + 1;
+  S.r = p; p += mmax + 1;
+  S.xpp = p; p += mmax + 1;
+  S.carry = p; p += 2 * (nmax / 64) + 8;
+  S.red = p;
+  return S;
+}
+
+// Dot product of a[lo..hi) and b[lo..hi) by one wave (four independent
+// accumulators per lane, fixed combination order).
+__device__ __forceinline__ double wave_dot(const double *__restrict__ a, const double *__restrict__ b,
+                                           int lo, int hi, int lane) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = lo + lane;
+  for (; i + 3 * kWave < hi; i += 4 * kWave) {
+    a0 = fma(a[i], b[i], a0);
+    a1 = fma(a[i + kWave], b[i + kWave], a1);
+    a2 = fma(a[i + 2 * kWave], b[i + 2 * kWave], a2);
+    a3 = fma(a[i + 3 * kWave], b[i + 3 * kWave], a3);
+  }
+  for (; i < hi; i += kWave) a0 = fma(a[i], b[i], a0);
+  return wave_sum((a0 + a1) + (a2 + a3));
+}
+
+// Row-tile product over a column-major matrix M (ld ldm): for 16 rows
+// [i0, i0+16) and 4 column phases per wave, acc(i) = sum_l M[i + l ld] x[l]
+// over l in [l0, l1) with the per-row predicate lo(i) <= l <= hi(i).
+// Returns the full sum in every lane of row i (lanes i%16, +16, +32, +48).
+template <int MODE>  // 0: no predicate, 1: l <= i (lower), 2: l >= i (upper)
+__device__ __forceinline__ double tile_rowdot(const double *__restrict__ Mx, size_t ldm,
+                                              const double *__restrict__ x, int i, bool row_ok,
+                                              int l0, int l1, int cp) {
+  double a0 = 0.0, a1 = 0.0;
+  if (row_ok) {
+    int l = l0 + cp;
+    for (; l + 4 < l1; l += 8) {
+      double m0 = Mx[(size_t)i + (size_t)l * ldm];
+      double m1 = Mx[(size_t)i + (size_t)(l + 4) * ldm];
+      if (MODE == 1) { if (l > i) m0 = 0.0; if (l + 4 > i) m1 = 0.0; }
+      if (MODE == 2) { if (l < i) m0 = 0.0; if (l + 4 < i) m1 = 0.0; }
+      a0 = fma(m0, x[l], a0);
+      a1 = fma(m1, x[l + 4], a1);
+    }
+    for (; l < l1; l += 4) {
+      double m0 = Mx[(size_t)i + (size_t)l * ldm];
+      if (MODE == 1 && l > i) m0 = 0.0;
+      if (MODE == 2 && l < i) m0 = 0.0;
+      a0 = fma(m0, x[l], a0);
+    }
+  }
+  double acc = a0 + a1;
+  acc += __shfl_xor(acc, 16, kWave);
+  acc += __shfl_xor(acc, 32, kWave);
+  return acc;
+}
+
+// Two vectors through one pass (P5).
+__device__ __forceinline__ void tile_rowdot2_upper(const double *__restrict__ Mx, size_t ldm,
+                                                   const double *__restrict__ x,
+                                                   const double *__restrict__ y, int i,
+                                                   bool row_ok, int l0, int l1, int cp,
+                                                   double &ox, double &oy) {
+  double ax = 0.0, ay = 0.0;
+  if (row_ok) {
+    for (int l = l0 + cp; l < l1; l += 4) {
+      double mv = Mx[(size_t)i + (size_t)l * ldm];
+      if (l < i) mv = 0.0;
+      ax = fma(mv, x[l], ax);
+      ay = fma(mv, y[l], ay);
+    }
+  }
+  ax += __shfl_xor(ax, 16, kWave);
+  ax += __shfl_xor(ax, 32, kWave);
+  ay += __shfl_xor(ay, 16, kWave);
+  ay += __shfl_xor(ay, 32, kWave);
+  ox = ax;
+  oy = ay;
+}
+
+// Sum over the group of per-lane partials `part`: WG partial to red[rank],
+// barrier, then every WG sums red[0..size) in the same fixed order.
+// Returns false on abort.
+__device__ bool grp_sum(Ctx &c, double part, double *red, double &out) {
+  __shared__ double s_w[kChainWaves];
+  __shared__ double s_tot;
+  part = wave_sum(part);
+  if (c.lane == 0) s_w[c.wave] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kChainWaves; q++) t += s_w[q];
+    red[c.rank] = t;
+  }
+  if (!grp_sync(c)) return false;
+  if (c.wave == 0) {
+    double t = 0.0;
+    for (int r = c.lane; r < c.size; r += kWave) t += red[r];
+    t = wave_sum(t);
+    if (c.lane == 0) s_tot = t;
+  }
+  __syncthreads();
+  out = s_tot;
+  return true;
+}
+
+struct CView {
+  int n, m, M, s0;
+  double *Y;            // column l at Y + l * n
+  double *T;            // T[p, l] at T[p + l * ldt]
+  size_t ldt;
+  double *Z;            // column-major, ldz
+  size_t ldz;
+  const double *W;
+  const double *Ll, *Lu1i, *Lu2, *Lu3;   // + s0: member c at offset c, stride m
+  const unsigned char *Lsw;
+};
+
+// Solve (T - lambda I) v = q/||q|| with the stored LU of member c; run by one
+// whole workgroup.  The forward sweep is a scan of the affine maps
+// cur_{i+1} = A_i cur_i + B_i (|A_i| <= 1 under partial pivoting, so the
+// scan is as stable as the recurrence); the back sweep is sequential in wave 0.
+__device__ void wg_solve(const CView &cv, int c, const double *__restrict__ q, double *__restrict__ v,
+                         const Scr &S, int wave, int lane) {
+  const int n = cv.n;
+  const size_t m = (size_t)cv.m;
+  const int tid = threadIdx.x;
+  const double *__restrict__ Ll = cv.Ll + c;
+  const double *__restrict__ U1 = cv.Lu1i + c;
+  const double *__restrict__ U2 = cv.Lu2 + c;
+  const double *__restrict__ U3 = cv.Lu3 + c;
+  const unsigned char *__restrict__ SW = cv.Lsw + c;
+  __shared__ double s_w[kChainWaves];
+  __shared__ double s_rn;
+  __shared__ double st_u2[kWave], st_u3[kWave], st_y[kWave], st_x[kWave];
+
+  // 1/||q||
+  double ss = 0.0;
+  for (int i = tid; i < n; i += kChainThreads) ss = fma(q[i], q[i], ss);
+  ss = wave_sum(ss);
+  if (lane == 0) s_w[wave] = ss;
+  __syncthreads();
+  if (tid == 0) s_rn = 1.0 / sqrt((s_w[0] + s_w[1]) + (s_w[2] + s_w[3]));
+  __syncthreads();
+  const double rn = s_rn;
+
+  // forward maps for rows 0..n-2, scanned in chunks of 64
+  const int nmaps = n - 1;
+  const int nch = (nmaps + kWave - 1) / kWave;
+  for (int k = wave; k < nch; k += kChainWaves) {
+    const int i = k * kWave + lane;
+    double A = 1.0, B = 0.0;
+    if (i < nmaps) {
+      const double bn = q[i + 1] * rn;
+      const double l = Ll[(size_t)i * m];
+      if (SW[(size_t)i * m]) { A = 1.0; B = -(l * bn); }
+      else { A = -l; B = bn; }
+    }
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const double Ap = __shfl_up(A, off, kWave);
+      const double Bp = __shfl_up(B, off, kWave);
+      if (lane >= off) { B = fma(A, Bp, B); A = A * Ap; }
+    }
+    if (i < nmaps) { S.P[i] = A; S.Q[i] = B; }
+    if (lane == kWave - 1) { S.carry[2 * k] = A; S.carry[2 * k + 1] = B; }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // carries into each chunk: cur_{64k}; stored over the chunk summaries
+    double cur = q[0] * rn;
+    for (int k = 0; k < nch; k++) {
+      const double A = S.carry[2 * k], B = S.carry[2 * k + 1];
+      S.carry[2 * k] = cur;
+      cur = fma(A, cur, B);
+    }
+    S.carry[2 * nch] = cur;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += kChainThreads) {
+    const int k = i / kWave;
+    const double ck = S.carry[2 * k];
+    const double cur = (i % kWave == 0) ? ck : fma(S.P[i - 1], ck, S.Q[i - 1]);
+    double y = cur;
+    if (i < nmaps && SW[(size_t)i * m]) y = q[i + 1] * rn;
+    v[i] = y * U1[(size_t)i * m];
+  }
+  __syncthreads();
+
+  // back substitution, sequential in wave 0, 64 rows per staged block
+  if (wave == 0) {
+    double x1 = 0.0, x2 = 0.0;
+    int hi = n;
+    int lo = hi - kWave > 0 ? hi - kWave : 0;
+    double pu2 = 0.0, pu3 = 0.0, py = 0.0;
+    if (lo + lane < hi) {
+      const size_t o = (size_t)(lo + lane) * m;
+      pu2 = U2[o]; pu3 = U3[o]; py = v[lo + lane];
+    }
+    while (hi > 0) {
+      st_u2[lane] = pu2; st_u3[lane] = pu3; st_y[lane] = py;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int nlo = lo - kWave > 0 ? lo - kWave : 0;
+      if (lo > 0 && nlo + lane < lo) {
+        const size_t o = (size_t)(nlo + lane) * m;
+        pu2 = U2[o]; pu3 = U3[o]; py = v[nlo + lane];
+      }
+      for (int tt = hi - lo - 1; tt >= 0; tt--) {
+        const double x = fma(-st_u2[tt], x1, fma(-st_u3[tt], x2, st_y[tt]));
+        x2 = x1;
+        x1 = x;
+        if (lane == tt) st_x[tt] = x;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lo + lane < hi) v[lo + lane] = st_x[lane];
+      __builtin_amdgcn_wave_barrier();
+      hi = lo;
+      lo = nlo;
+    }
+  }
+  __syncthreads();
+}
+
+// Runs the chain of one cluster with the group described by ctx.  Returns
+// false if the run was aborted.
+__device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr &S, int iters) {
+  CView cv;
+  cv.n = P.n; cv.m = P.m; cv.M = it.size; cv.s0 = it.start;
+  cv.Y = P.Y + (size_t)it.start * P.n;
+  cv.ldt = (size_t)P.m;
+  cv.T = P.T + (size_t)it.start + (size_t)it.start * cv.ldt;
+  cv.Z = P.Z + (size_t)it.start * P.ldz;
+  cv.ldz = (size_t)P.ldz;
+  cv.W = P.W + it.start;
+  cv.Ll = P.Ll + it.start; cv.Lu1i = P.Lu1i + it.start;
+  cv.Lu2 = P.Lu2 + it.start; cv.Lu3 = P.Lu3 + it.start;
+  cv.Lsw = P.Lsw + it.start;
+  const int n = cv.n;
+  const int tid = threadIdx.x, lane = cx.lane;
+  const int gtid = cx.rank * kChainThreads + tid, gthreads = cx.size * kChainThreads;
+  __shared__ double s_sc[4];
+
+  // Y_1, T_1 from the first member's unit vector z (Alg. 4, first step of the
+  // second member): c_1 = -sgn(z_0)||z||, y_1 = z - c_1 e_0, t_1 = 1/(c_1^2 - z_0 c_1).
+  {
+    const double *z = cv.Z;
+    double part = 0.0;
+    for (int i = gtid; i < n; i += gthreads) part = fma(z[i], z[i], part);
+    double nz2;
+    if (!grp_sum(cx, part, S.red, nz2)) return false;
+    const double z0 = z[0];
+    const double g = -(z0 >= 0.0 ? 1.0 : -1.0) * sqrt(nz2);
+    for (int i = gtid; i < n; i += gthreads) cv.Y[i] = (i == 0) ? z0 - g : z[i];
+    if (gtid == 0) cv.T[0] = (g == 0.0) ? 0.0 : 1.0 / (g * g - z0 * g);
+    if (!grp_sync(cx)) return false;
+  }
+
+  for (int c = 1; c < cv.M; c++) {
+    const double *vin = cv.Z + (size_t)c * cv.ldz;   // raw first-iteration solve
+    for (int k = 1; k <= iters; k++) {
+      // P1: x = Y_c^T v
+      for (int l = cx.gw; l < c; l += cx.nw) {
+        const double acc = wave_dot(cv.Y + (size_t)l * n, vin, l, n, lane);
+        if (lane == 0) S.x[l] = acc;
+      }
+      if (!grp_sync(cx)) return false;
+      // P2: x' = T_c^T x
+      for (int l = cx.gw; l < c; l += cx.nw) {
+        const double acc = wave_dot(cv.T + (size_t)l * cv.ldt, S.x, 0, l + 1, lane);
+        if (lane == 0) S.xp[l] = acc;
+      }
+      if (!grp_sync(cx)) return false;
+      // P3: u = v_hat - Yhat_c x' over rows c..n-1, and ||u||^2
+      double part = 0.0;
+      {
+        const int nt = (n - c + 15) / 16;
+        const int rr = lane & 15, cp = lane >> 4;
+        for (int t = cx.gw; t < nt; t += cx.nw) {
+          const int i = c + t * 16 + rr;
+          const bool ok = i < n;
+          const double acc = tile_rowdot<0>(cv.Y, (size_t)n, S.xp, i, ok, 0, c, cp);
+          if (ok && cp == 0) {
+            const double ui = vin[i] - acc;
+            S.u[i] = ui;
+            part = fma(ui, ui, part);
+          }
+        }
+      }
+      double beta2;
+      if (!grp_sum(cx, part, S.red, beta2)) return false;
+      // P4: Householder vector and s = Yhat_c^T y_hat
+      const double alpha = S.u[c];
+      const double beta = sqrt(beta2);
+      const double gam = -(alpha >= 0.0 ? 1.0 : -1.0) * beta;
+      const double tj = (gam == 0.0) ? 0.0 : 1.0 / (gam * gam - alpha * gam);
+      const double yc = alpha - gam;
+      for (int l = cx.gw; l < c; l += cx.nw) {
+        const double *col = cv.Y + (size_t)l * n;
+        double acc = wave_dot(col, S.u, c + 1, n, lane);
+        if (lane == 0) {
+          const double rl = col[c];
+          S.s[l] = fma(rl, yc, acc);
+          S.r[l] = rl;
+        }
+      }
+      {
+        double *ycol = cv.Y + (size_t)c * n;
+        for (int i = c + gtid; i < n; i += gthreads) ycol[i] = (i == c) ? yc : S.u[i];
+        if (gtid == 0) cv.T[(size_t)c + (size_t)c * cv.ldt] = tj;
+      }
+      if (!grp_sync(cx)) return false;
+      // P5: t_hat = -t_j T_c s (column c of T) and x'' = T_{c+1} r
+      {
+        const int nt = (c + 15) / 16;
+        const int rr = lane & 15, cp = lane >> 4;
+        for (int t = cx.gw; t < nt; t += cx.nw) {
+          const int p = t * 16 + rr;
+          const bool ok = p < c;
+          double ts, tr;
+          tile_rowdot2_upper(cv.T, cv.ldt, S.s, S.r, p, ok, t * 16, c, cp, ts, tr);
+          if (ok && cp == 0) {
+            const double th = -tj * ts;
+            cv.T[(size_t)p + (size_t)c * cv.ldt] = th;
+            S.xpp[p] = fma(th, yc, tr);
+          }
+        }
+        if (gtid == 0) S.xpp[c] = tj * yc;
+      }
+      if (!grp_sync(cx)) return false;
+      // P6: q = Y_{c+1} x'' - e_c
+      double *qout = (k == iters) ? (cv.Z + (size_t)c * cv.ldz) : S.q;
+      {
+        const int nt = (n + 15) / 16;
+        const int rr = lane & 15, cp = lane >> 4;
+        for (int t = cx.gw; t < nt; t += cx.nw) {
+          const int i0 = t * 16;
+          const int i = i0 + rr;
+          const bool ok = i < n;
+          const int l1 = (i0 + 15 < c ? i0 + 15 : c) + 1;
+          const double acc = tile_rowdot<1>(cv.Y, (size_t)n, S.xpp, i, ok, 0, l1, cp);
+          if (ok && cp == 0) qout[i] = (i == c) ? acc - 1.0 : acc;
+        }
+      }
+      if (!grp_sync(cx)) return false;
+      if (k < iters) {
+        // P7: next iterate
+        if (cx.rank == 0) wg_solve(cv, c, S.q, S.v, S, cx.wave, lane);
+        if (!grp_sync(cx)) return false;
+        vin = S.v;
+      }
+    }
+  }
+  (void)s_sc;
+  return true;
+}
+
+// Small clusters: one workgroup per cluster, items taken from a work counter.
+__global__ void __launch_bounds__(kChainThreads) k_chain_small(const Prob *__restrict__ probs,
+                                                               const ChainItem *__restrict__ items,
+                                                               int nitems, int *counter,
+                                                               ChainScratch scr, int iters) {
+  __shared__ int s_item;
+  Ctx cx;
+  cx.rank = 0; cx.size = 1; cx.bar = nullptr; cx.target = 0; cx.abort_flag = nullptr;
+  cx.wave = threadIdx.x / kWave; cx.lane = threadIdx.x % kWave;
+  cx.gw = cx.wave; cx.nw = kChainWaves;
+  double *base = scr.base + (size_t)blockIdx.x * scr.stride;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int idx = s_item;
+    __syncthreads();
+    if (idx >= nitems) break;
+    const ChainItem it = items[idx];
+    const Prob &P = probs[it.prob];
+    const Scr S = make_scr(base, P.n, P.m);
+    run_chain(cx, P, it, S, iters);
+  }
+}
+
+hipError_t launch_chain_small(const Prob *probs, const ChainItem *items, int nitems, int *counter,
+                              ChainScratch scr, int nwg, int iters, hipStream_t s) {
+  if (nitems <= 0 || nwg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chain_small, dim3(nwg), dim3(kChainThreads), 0, s, probs, items, nitems,
+                     counter, scr, iters);
+  return hipGetLastError();
+}
+
+// Large clusters: cooperative launch; workgroup w belongs to group
+// wg_group[w] and runs that group's items in order with group barriers.
+__global__ void __launch_bounds__(kChainThreads) k_chain_coop(const Prob *__restrict__ probs,
+                                                              const ChainItem *__restrict__ items,
+                                                              const Group *__restrict__ groups,
+                                                              const int *__restrict__ wg_group,
+                                                              unsigned *bars, int *abort_flag,
+                                                              ChainScratch scr, int iters) {
+  const int g = wg_group[blockIdx.x];
+  if (g < 0) return;
+  const Group G = groups[g];
+  Ctx cx;
+  cx.rank = (int)blockIdx.x - G.wg0;
+  cx.size = G.nwg;
+  cx.bar = bars + g;
+  cx.target = 0;
+  cx.abort_flag = abort_flag;
+  cx.wave = threadIdx.x / kWave;
+  cx.lane = threadIdx.x % kWave;
+  cx.gw = cx.rank * kChainWaves + cx.wave;
+  cx.nw = cx.size * kChainWaves;
+  double *base = scr.base + (size_t)g * scr.stride;
+  for (int q = 0; q < G.nit; q++) {
+    const ChainItem it = items[G.it0 + q];
+    const Prob &P = probs[it.prob];
+    const Scr S = make_scr(base, P.n, P.m);
+    if (!run_chain(cx, P, it, S, iters)) return;
+    if (!grp_sync(cx)) return;   // scratch reuse across items
+  }
+}
+
+hipError_t launch_chain_coop(const Prob *probs, const ChainItem *items, const Group *groups,
+                             const int *wg_group, unsigned *bars, int *abort_flag,
+                             ChainScratch scr, int nwg, int iters, hipStream_t s) {
+  if (nwg <= 0) return hipSuccess;
+  void *args[] = {(void *)&probs, (void *)&items, (void *)&groups, (void *)&wg_group,
+                  (void *)&bars, (void *)&abort_flag, (void *)&scr, (void *)&iters};
+  return hipLaunchCooperativeKernel((const void *)k_chain_coop, dim3(nwg), dim3(kChainThreads),
+                                    args, 0, s);
+}
+
+int coop_max_wgs(int device) {
+  int ncu = 0, per = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain_coop,
+                                                   kChainThreads, 0) != hipSuccess)
+    return 0;
+  return ncu * per;
+}
+
+int small_max_wgs(int device) {
+  int ncu = 0, per = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain_small,
+                                                   kChainThreads, 0) != hipSuccess)
+    return 0;
+  return ncu * per;
+}
+
+// ---------------------------------------------------------------------------
+// a8: normalize each column, largest-magnitude entry positive (lowest index on
+// ties); flag non-finite vectors.  One wave per column.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_finalize(const Prob *__restrict__ probs, int nprob,
+                                                  const int64_t *__restrict__ loff, int64_t nlanes) {
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (wv >= nlanes) return;
+  const int b = find_prob(loff, nprob, wv);
+  const Prob &P = probs[b];
+  const int j = (int)(wv - loff[b]);
+  double *z = P.Z + (size_t)j * P.ldz;
+  const int n = P.n;
+  double ss = 0.0, best = -1.0;
+  int bi = 0x7fffffff;
+  for (int i = lane; i < n; i += kWave) {
+    const double v = z[i];
+    ss = fma(v, v, ss);
+    const double a = fabs(v);
+    if (a > best) { best = a; bi = i; }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ob = __shfl_xor(best, off, kWave);
+    const int oi = __shfl_xor(bi, off, kWave);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  ss = wave_sum(ss);
+  const bool finite = isfinite(ss) && ss > 0.0;
+  const double sgn = (bi < n && z[bi] < 0.0) ? -1.0 : 1.0;
+  const double sc = finite ? sgn / sqrt(ss) : 1.0;
+  for (int i = lane; i < n; i += kWave) z[i] = z[i] * sc;
+  if (P.info && lane == 0) {
+    P.info[1 + j] = finite ? 0 : 1;
+    if (!finite) atomicAdd(P.info, 1);
+  }
+}
+
+hipError_t launch_finalize(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
+                           hipStream_t s) {
+  if (nlanes <= 0) return hipSuccess;
+  const int64_t threads = nlanes * kWave;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, probs,
+                     nprob, loff, nlanes);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int *p, size_t n, int v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int *p, size_t n, int v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace te

@@ -1,0 +1,69 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point the
+public header declares, and rejects invalid arguments on the host (these
+calls return before any HIP runtime call, so no GPU is needed)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1209_1910_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tridiag_eigvecs.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|size_t|void)\s+\**\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.lib()
+    names = _declared()
+    assert len(names) >= 8
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(names) == set(binding.SYMBOLS)
+
+
+NULL = ctypes.c_void_p(0)
+P = ctypes.c_void_p(256)   # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((NULL, P, 10, 1, 10, P, P, 10, NULL), -1),
+    ((P, NULL, 10, 1, 10, P, P, 10, NULL), -2),
+    ((P, P, 0, 1, 1, P, P, 10, NULL), -3),
+    ((P, P, 10, 0, 10, P, P, 10, NULL), -4),
+    ((P, P, 10, 5, 4, P, P, 10, NULL), -5),
+    ((P, P, 10, 1, 11, P, P, 10, NULL), -5),
+    ((P, P, 10, 1, 10, NULL, P, 10, NULL), -6),
+    ((P, P, 10, 1, 10, P, NULL, 10, NULL), -7),
+    ((P, P, 10, 1, 10, P, P, 9, NULL), -8),
+])
+def test_tridiag_eigvecs_argument_errors(args, expect):
+    assert binding.lib().tridiag_eigvecs(*args) == expect
+
+
+def test_other_entry_points_argument_errors():
+    L = binding.lib()
+    assert L.tridiag_eigvecs_given_w(P, P, 10, 11, P, P, 10, NULL) == -4
+    assert L.tridiag_eigvecs_given_w(P, P, 10, 3, NULL, P, 10, NULL) == -5
+    assert L.tridiag_eigvecs_given_w(P, P, 10, 3, P, P, 5, NULL) == -7
+    assert L.tridiag_eigvals(P, P, 10, 3, 2, P, NULL) == -5
+    assert L.tridiag_clusters(P, 0, 1.0, P, P, P, NULL) == -2
+    assert L.tridiag_clusters(P, 4, -1.0, P, P, P, NULL) == -3
+    assert L.tridiag_eigvecs_workspace_bytes(10, 4, 3) == 0
+    assert L.tridiag_eigvecs_workspace_bytes(0, 1, 1) == 0
+    o = binding.te_opts()
+    o.iters = -1
+    assert L.tridiag_eigvecs_ex(P, P, 10, 1, 10, NULL, P, P, 10, ctypes.byref(o), P, 1 << 40,
+                                NULL, NULL) == -10
+    o.iters = 3
+    assert L.tridiag_eigvecs_ex(P, P, 10, 1, 10, NULL, P, P, 10, ctypes.byref(o), NULL, 1 << 40,
+                                NULL, NULL) == -11
