@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark: eigenvectors per second, FP64, at n = 16000.
+
+Workload: tridiag(-1, 2, -1) of order 16000, all 16000 eigenpairs (one
+Peters-Wilkinson cluster of 16000 members: every gap is below 1e-3 ||T||_1),
+3 inverse-iteration steps per vector.  One step = one tridiag_eigvecs call
+(bisection, clustering, first solves, the compact-WY chain, finalize) with
+d, e already resident in HBM.
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel
+(the cooperative compact-WY chain kernel, timed with HIP events on its launch
+stream by the library) and the CPU-oracle baseline on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+ITERS = 3
+
+
+def chain_alg_bytes(n: int, M: int, iters: int = ITERS) -> float:
+    """Algorithmic HBM bytes of one cluster chain (3 passes over Y + 2 over T per
+    compact-WY step, plus the column and vector writes), summed over members
+    c = 1..M-1 and `iters` steps each:
+      Y_c^T v          n c - c(c-1)/2
+      Yhat_c x', Yhat^T y_hat (one pass)   (n - c) c
+      Y_{c+1} x''      n (c+1) - c(c+1)/2
+      T_c^T x, T_c [s r]                   c (c+1)
+      writes: y column n - c, T column c + 1, q n
+    """
+    import numpy as np
+    c = np.arange(1, M, dtype=np.float64)
+    per = ((n * c - c * (c - 1) / 2) + (n - c) * c + (n * (c + 1) - c * (c + 1) / 2)
+           + c * (c + 1) + (n - c) + (c + 1) + n)
+    return float(8.0 * iters * per.sum())
+
+
+def cpu_baseline(n_sample: int, n_target: int):
+    import oracle
+    from paper_1209_1910_amd import inputs
+    oracle.build(force=False)
+    d, e = inputs.laplacian_tridiag(n_sample)
+    t0 = time.perf_counter()
+    oracle.eigvecs(d, e)
+    dt = time.perf_counter() - t0
+    scale = (n_target / n_sample) ** 3
+    return {
+        "value": n_target / (dt * scale),
+        "unit": "eigvecs/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"full oracle run (bisection, clustering, inverse iteration with compact WY) on "
+                   f"tridiag(-1,2,-1) n={n_sample}, {dt:.1f} s single-threaded on "
+                   f"{platform.processor() or platform.machine()}; time scaled by "
+                   f"(n/{n_sample})^3 to n={n_target} (extrapolated)"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=16000)
+    ap.add_argument("--cpu-n", type=int, default=1400, help="oracle sample size")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the per-GPU "
+              "path and its multi-GPU sharding plan are described in DESIGN.md", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1209_1910_amd import binding, inputs
+
+    if not torch.cuda.is_available():
+        print("no GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    n = args.n
+    d_np, e_np = inputs.workload_laplacian(n)
+    d = torch.from_numpy(d_np).to(dev)
+    e = torch.from_numpy(e_np).to(dev)
+    torch.cuda.synchronize()
+
+    print(f"[bench] n={n} warmup={args.warmup}", file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        W, Z = binding.tridiag_eigvecs(d, e)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1} done", file=sys.stderr, flush=True)
+
+    binding.te_timing_reset()
+    binding.te_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        W, Z = binding.tridiag_eigvecs(d, e)
+        torch.cuda.synchronize()
+        print(f"[bench] step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    binding.te_timing_enable(False)
+    phases = binding.te_timing_read()
+
+    total = t1 - t0
+    ms_per_step = 1000.0 * total / args.steps
+    value = n * args.steps / total
+
+    # cluster structure of this run -> algorithmic bytes of the chain kernel
+    norm1 = float(np.max(np.abs(d_np) + np.concatenate([[0.0], np.abs(e_np)])
+                         + np.concatenate([np.abs(e_np), [0.0]])))
+    st, sz = binding.tridiag_clusters(W, 1e-3 * norm1)
+    sizes = sz.cpu().numpy()
+    large = [int(M) for M in sizes if M >= 2 and M * n >= (1 << 20)]
+    alg_bytes = sum(chain_alg_bytes(n, M) for M in large)
+    coop_ms, coop_cnt = phases["chain_coop"]
+    per_launch_s = (coop_ms / max(coop_cnt, 1)) / 1000.0
+    achieved = alg_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
+
+    out = {
+        "metric": "eigvecs/s FP64 at n=16k",
+        "value": value,
+        "unit": "eigvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"tridiag(-1,2,-1) n={n}, all {n} eigenpairs, one cluster, "
+                               f"{ITERS} inverse-iteration steps, compact-WY re-orthogonalization",
+                   "n": n, "m": n, "clusters": int(len(sizes)), "largest_cluster": int(sizes.max())},
+        "roofline": {"bound": "hbm", "kernel": "k_chain_coop", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "alg_bytes_per_launch": alg_bytes,
+                     "launch_ms": per_launch_s * 1000.0},
+        "phases_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in phases.items()},
+    }
+    if not args.no_cpu_baseline:
+        print(f"[bench] cpu baseline: oracle n={args.cpu_n}", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, n)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -136,6 +136,18 @@ int tridiag_eigvals(const double *d, const double *e, int n, int il, int iu, dou
 int tridiag_clusters(const double *W, int m, double tol, int *start, int *size, int *ncl,
                      hipStream_t stream);
 
+/* Device-time accounting of the library's kernels, for benchmarks and
+ * profiling.  When enabled, every entry point records hipEvents around each
+ * kernel it launches, on the stream it launches it on, and adds the elapsed
+ * milliseconds to per-phase totals (process-wide, guarded by a mutex).
+ * Phases: 0 setup, 1 bisection, 2 clusters, 3 first solves (one lane per
+ * eigenvalue), 4 transpose, 5 small cluster chains, 6 cooperative cluster
+ * chains, 7 finalize.  te_timing_read copies min(cap, 8) totals and launch
+ * counts (either pointer may be NULL) and returns 8. */
+void te_timing_enable(int on);
+void te_timing_reset(void);
+int te_timing_read(double *ms, long long *launches, int cap);
+
 /* HIP error code of the last runtime failure seen by this thread (0 if none). */
 int te_last_hip_error(void);
 

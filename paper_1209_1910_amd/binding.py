@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(HERE, "libtridiag_eigvecs.so")
 TE_DEFAULT_SEED = 0x12091910
 SYMBOLS = ("tridiag_eigvecs", "tridiag_eigvecs_given_w", "tridiag_eigvecs_workspace_bytes",
            "tridiag_eigvecs_ex", "tridiag_eigvecs_batched", "tridiag_eigvals", "tridiag_clusters",
-           "te_last_hip_error")
+           "te_timing_enable", "te_timing_reset", "te_timing_read", "te_last_hip_error")
+PHASES = ("setup", "bisect", "clusters", "first_solves", "transpose", "chain_small",
+          "chain_coop", "finalize")
 
 
 class TeError(RuntimeError):
@@ -56,6 +58,11 @@ def lib():
                                               ctypes.POINTER(te_opts), _vp]
         L.tridiag_eigvals.argtypes = [_vp, _vp, i, i, i, _vp, _vp]
         L.tridiag_clusters.argtypes = [_vp, i, ctypes.c_double, _vp, _vp, _vp, _vp]
+        L.te_timing_enable.argtypes = [i]
+        L.te_timing_enable.restype = None
+        L.te_timing_reset.restype = None
+        L.te_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_longlong), i]
         L.te_last_hip_error.restype = i
         _lib = L
     return _lib
@@ -167,6 +174,22 @@ def tridiag_clusters(W, tol, stream=None, device="cuda"):
     _check("tridiag_clusters", rc)
     k = int(ncl.item())
     return start[:k], size[:k]
+
+
+def te_timing_enable(on=True):
+    lib().te_timing_enable(1 if on else 0)
+
+
+def te_timing_reset():
+    lib().te_timing_reset()
+
+
+def te_timing_read():
+    """Per-phase device milliseconds and launch counts since the last reset."""
+    ms = (ctypes.c_double * 8)()
+    cnt = (ctypes.c_longlong * 8)()
+    k = lib().te_timing_read(ms, cnt, 8)
+    return {PHASES[p]: (ms[p], cnt[p]) for p in range(min(k, 8))}
 
 
 def tridiag_eigvecs_workspace_bytes(n, il, iu):

@@ -27,8 +27,61 @@ inline int hip_fail(hipError_t e) {
     if (_e != hipSuccess) return hip_fail(_e);  \
   } while (0)
 
+// ---- per-phase device timing (hipEvents on the launch stream) ----
+enum Phase { PH_SETUP, PH_BISECT, PH_CLUSTER, PH_INVIT, PH_TRANSPOSE, PH_SMALL, PH_COOP,
+             PH_FINAL, PH_COUNT };
+
+std::mutex g_tmu;
+bool g_timing = false;
+double g_ms[PH_COUNT] = {};
+long long g_cnt[PH_COUNT] = {};
+
+struct PhaseTimer {
+  bool on;
+  hipStream_t s;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  explicit PhaseTimer(hipStream_t st) : s(st) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    on = g_timing;
+  }
+  void begin(int ph) {
+    if (!on) return;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    (void)hipEventRecord(a, s);
+    ev.push_back({ph, {a, b}});
+  }
+  void end() {
+    if (!on || ev.empty()) return;
+    (void)hipEventRecord(ev.back().second.second, s);
+  }
+  // Call after the stream has been synchronized.
+  void collect() {
+    if (!on) return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &x : ev) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, x.second.first, x.second.second) == hipSuccess) {
+        g_ms[x.first] += ms;
+        g_cnt[x.first] += 1;
+      }
+    }
+    release();
+  }
+  void release() {
+    for (auto &x : ev) {
+      (void)hipEventDestroy(x.second.first);
+      (void)hipEventDestroy(x.second.second);
+    }
+    ev.clear();
+  }
+  ~PhaseTimer() { release(); }
+};
+
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+inline size_t even(size_t x) { return (x + 1) & ~(size_t)1; }
 
 // A cluster goes to the cooperative kernel when its Y block (n x size doubles)
 // exceeds this many entries; smaller chains run one per workgroup.
@@ -66,6 +119,14 @@ DeviceLimits limits() {
   std::lock_guard<std::mutex> lk(mu);
   if (dev < 0 || dev >= 64) return DeviceLimits{};
   if (cache[dev].device != dev) {
+    // Keep freed stream-ordered allocations in the device's default pool, so
+    // repeated calls do not map and unmap their (possibly tens of GB of)
+    // workspace every time.
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
     DeviceLimits L;
     L.device = dev;
     L.coop = coop_max_wgs(dev);
@@ -77,9 +138,10 @@ DeviceLimits limits() {
 
 // Per-problem sizes of the workspace pieces (bytes, each aligned).
 struct ProbLayout {
-  size_t e2, nrm, pos, cls, clz, ncl, V, Ll, U1, U2, U3, Sw, Y, T, prm, info;
+  size_t e2, nrm, pos, cls, clz, ncl, V, Ll, U1, U2, U3, Sw, Lrec, Lswb, Y, Yr, T, Tr, prm, info;
   size_t total() const {
-    return e2 + nrm + pos + cls + clz + ncl + V + Ll + U1 + U2 + U3 + Sw + Y + T + prm + info;
+    return e2 + nrm + pos + cls + clz + ncl + V + Ll + U1 + U2 + U3 + Sw + Lrec + Lswb + Y + Yr + T +
+           Tr + prm + info;
   }
 };
 
@@ -98,8 +160,13 @@ ProbLayout prob_layout(int n, int m) {
   L.U2 = L.V;
   L.U3 = L.V;
   L.Sw = align_up(nm);
-  L.Y = L.V;
-  L.T = align_up(sizeof(double) * (size_t)m * (size_t)m);
+  L.Lrec = align_up(4 * sizeof(double) * nm);
+  L.Lswb = align_up(nm);
+  const size_t ldy = even((size_t)n), ldm = even((size_t)m);
+  L.Y = align_up(sizeof(double) * ldy * (size_t)m);
+  L.Yr = align_up(sizeof(double) * (size_t)n * ldm);
+  L.T = align_up(sizeof(double) * ldm * ldm);
+  L.Tr = L.T;
   L.prm = align_up(sizeof(Params));
   L.info = align_up(sizeof(int) * ((size_t)m + 1));
   return L;
@@ -145,7 +212,7 @@ size_t chain_bytes(int nmax, int mmax, int nslots, int coop_wgs, int nitems) {
   b += align_up(sizeof(ChainItem) * (size_t)std::max(nitems, 1));
   b += align_up(sizeof(Group) * (size_t)std::max(coop_wgs, 1));
   b += align_up(sizeof(int) * (size_t)std::max(coop_wgs, 1));      // wg_group
-  b += align_up(sizeof(unsigned) * (size_t)std::max(coop_wgs, 1)); // barriers
+  b += align_up(sizeof(unsigned) * kBarWords * (size_t)std::max(coop_wgs, 1)); // barriers
   b += align_up(sizeof(int) * 2);                                  // abort flag, counter
   return b;
 }
@@ -271,8 +338,14 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
     P.Lu2 = cv.take<double>(sizeof(double) * nm);
     P.Lu3 = cv.take<double>(sizeof(double) * nm);
     P.Lsw = cv.take<unsigned char>(nm);
-    P.Y = cv.take<double>(sizeof(double) * nm);
-    P.T = cv.take<double>(sizeof(double) * (size_t)m * m);
+    P.Lrec = cv.take<double>(4 * sizeof(double) * nm);
+    P.Lswb = cv.take<unsigned char>(nm);
+    P.ldy = (int)even((size_t)n);
+    P.ldm = (int)even((size_t)m);
+    P.Y = cv.take<double>(sizeof(double) * (size_t)P.ldy * m);
+    P.Yr = cv.take<double>(sizeof(double) * (size_t)n * P.ldm);
+    P.T = cv.take<double>(sizeof(double) * (size_t)P.ldm * P.ldm);
+    P.Tr = cv.take<double>(sizeof(double) * (size_t)P.ldm * P.ldm);
     P.prm = cv.take<Params>(sizeof(Params));
     int *pinfo = cv.take<int>(sizeof(int) * ((size_t)m + 1));
     P.info = (info && nprob == 1) ? info : pinfo;
@@ -289,12 +362,23 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   }
 
   // a1-a6
+  PhaseTimer tm(stream);
+  tm.begin(PH_SETUP);
   TE_CHECK(launch_setup(R.dprobs, nprob, stream));
+  tm.end();
+  tm.begin(PH_BISECT);
   if (W_given) TE_CHECK(launch_copy_w(R.dprobs, nprob, R.dloff, R.mtotal, W_given, stream));
   else TE_CHECK(launch_bisect(R.dprobs, nprob, R.dloff, R.mtotal, stream));
+  tm.end();
+  tm.begin(PH_CLUSTER);
   TE_CHECK(launch_cluster(R.dprobs, nprob, stream));
+  tm.end();
+  tm.begin(PH_INVIT);
   TE_CHECK(launch_invit(R.dprobs, nprob, R.dloff, R.mtotal, opt.iters, opt.seed, stream));
+  tm.end();
+  tm.begin(PH_TRANSPOSE);
   TE_CHECK(launch_transpose(R.dprobs, nprob, R.nmax, R.mmax, stream));
+  tm.end();
 
   // Cluster tables back to the host for the chain plan.
   std::vector<int> ncl(nprob);
@@ -363,7 +447,7 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   ChainItem *ditems = cc.take<ChainItem>(sizeof(ChainItem) * std::max(nitems, 1));
   Group *dgroups = cc.take<Group>(sizeof(Group) * std::max(coop_nwg, 1));
   int *dwg = cc.take<int>(sizeof(int) * std::max(coop_nwg, 1));
-  unsigned *dbars = cc.take<unsigned>(sizeof(unsigned) * std::max(coop_nwg, 1));
+  unsigned *dbars = cc.take<unsigned>(sizeof(unsigned) * kBarWords * std::max(coop_nwg, 1));
   int *dflags = cc.take<int>(sizeof(int) * 2);   // [0] abort, [1] work counter
 
   std::vector<ChainItem> all_items(small_items);
@@ -372,9 +456,12 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
     TE_CHECK(hipMemcpyAsync(ditems, all_items.data(), sizeof(ChainItem) * nitems,
                             hipMemcpyHostToDevice, stream));
   TE_CHECK(launch_fill_i32(dflags, 2, 0, stream));
-  if (small_nwg > 0)
+  if (small_nwg > 0) {
+    tm.begin(PH_SMALL);
     TE_CHECK(launch_chain_small(R.dprobs, ditems, (int)small_items.size(), dflags + 1, scr,
                                 small_nwg, opt.iters, stream));
+    tm.end();
+  }
   if (!groups.empty()) {
     std::vector<Group> g2(groups);
     for (auto &G : g2) G.it0 += (int)small_items.size();
@@ -382,14 +469,19 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
                             stream));
     TE_CHECK(hipMemcpyAsync(dwg, wg_group.data(), sizeof(int) * coop_nwg, hipMemcpyHostToDevice,
                             stream));
-    TE_CHECK(launch_fill_i32((int *)dbars, (size_t)coop_nwg, 0, stream));
+    TE_CHECK(launch_fill_i32((int *)dbars, kBarWords * (size_t)coop_nwg, 0, stream));
+    tm.begin(PH_COOP);
     TE_CHECK(launch_chain_coop(R.dprobs, ditems, dgroups, dwg, dbars, dflags, scr, coop_nwg,
                                opt.iters, stream));
+    tm.end();
   }
+  tm.begin(PH_FINAL);
   TE_CHECK(launch_finalize(R.dprobs, nprob, R.dloff, R.mtotal, stream));
+  tm.end();
   int abort_flag = 0;
   TE_CHECK(hipMemcpyAsync(&abort_flag, dflags, sizeof(int), hipMemcpyDeviceToHost, stream));
   TE_CHECK(hipStreamSynchronize(stream));
+  tm.collect();
   if (own) {
     TE_CHECK(hipFreeAsync(cbase, stream));
     TE_CHECK(hipFreeAsync(base, stream));
@@ -406,6 +498,25 @@ using namespace te;
 extern "C" {
 
 int te_last_hip_error(void) { return g_last_hip; }
+
+void te_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_timing = on != 0;
+}
+
+void te_timing_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (int p = 0; p < PH_COUNT; p++) { g_ms[p] = 0.0; g_cnt[p] = 0; }
+}
+
+int te_timing_read(double *ms, long long *launches, int cap) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (int p = 0; p < PH_COUNT && p < cap; p++) {
+    if (ms) ms[p] = g_ms[p];
+    if (launches) launches[p] = g_cnt[p];
+  }
+  return PH_COUNT;
+}
 
 int tridiag_eigvecs(const double *d, const double *e, int n, int il, int iu, double *W, double *Z,
                     int ldz, hipStream_t stream) {

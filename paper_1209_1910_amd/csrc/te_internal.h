@@ -9,8 +9,6 @@
 namespace te {
 
 constexpr int kWave = 64;            // CDNA wavefront width
-constexpr int kChainThreads = 256;   // 4 waves per chain workgroup
-constexpr int kChainWaves = kChainThreads / kWave;
 
 // Per-problem scalars from the setup pass.
 struct Params {
@@ -45,8 +43,16 @@ struct Prob {
   int *cl_start;        // m: cluster starts (first *ncl valid)
   int *cl_size;         // m
   int *ncl;             // 1
-  double *Y;            // n * m: compact-WY Y, cluster column l at (start + l) * n
-  double *T;            // m * m: compact-WY T, column-major ld m (diagonal blocks)
+  double *Lrec;         // n * m * 4: member-major LU records {l, 1/u1, u2/u1, u3/u1},
+                        //   eigenvalue j row i at (j * n + i) * 4 (later cluster members)
+  unsigned char *Lswb;  // n * m: member-major swap flags, j * n + i
+  double *Y;            // ldy * m: compact-WY Y column-major; cluster column l at
+                        //   (start + l) * ldy
+  double *Yr;           // n * ldm: the same Y row-major; cluster row i at i * ldm + start
+  double *T;            // ldm * m: compact-WY T column-major (diagonal blocks)
+  double *Tr;           // m * ldm: the same T row-major
+  int ldy;              // n rounded up to even (16-byte aligned columns)
+  int ldm;              // m rounded up to even
   int *info;            // 1 + m (may be null)
   int n, m, ldz;
   int kbase;            // global 1-based index of W[0] (start-vector key)
@@ -74,6 +80,7 @@ struct ChainScratch {
 };
 
 size_t chain_scratch_doubles(int nmax, int mmax, int nwg_in_group);
+constexpr size_t kBarWords = 32;     // unsigned words of barrier state per group
 
 // Launch helpers (te_kernels.hip).  Multi-problem kernels map a flat lane
 // index t to (problem b, index j) through loff (nprob + 1 prefix offsets).

@@ -369,36 +369,58 @@ hipError_t launch_invit(const Prob *probs, int nprob, const int64_t *loff, int64
 }
 
 // ---------------------------------------------------------------------------
-// V (interleaved) -> Z (column-major).  Singletons and first cluster members
-// are normalized here (the first member's unit vector seeds Y_1, T_1); later
-// members keep the raw first-iteration solve, the input of their first
-// compact-WY step.
+// V (interleaved) -> Z (column-major), and the LU factors of every later
+// cluster member (interleaved) -> one contiguous record per row and member
+// ({l, 1/u1, u2/u1, u3/u1} and the swap flag), the layout the sequential
+// chain solves stream.  Singletons and first cluster members are normalized
+// here (the first member's unit vector seeds Y_1, T_1); later members keep
+// the raw first-iteration solve, the input of their first compact-WY step.
+// 32 x 32 tiles through LDS.
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) k_transpose(const Prob *__restrict__ probs) {
   const Prob &P = probs[blockIdx.z];
   const int n = P.n, m = P.m;
-  const int j0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
+  const int j0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
   if (j0 >= m || i0 >= n) return;
-  __shared__ double tile[64][65];
-  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
-  for (int r = ty; r < 64; r += 4) {
+  __shared__ double tv[32][33], tl[32][33], t1[32][33], t2[32][33], t3[32][33];
+  __shared__ unsigned char tsw[32][33];
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  for (int r = ty; r < 32; r += 8) {
     const int i = i0 + r, j = j0 + tx;
-    if (i < n && j < m) tile[r][tx] = P.V[(size_t)i * m + j];
+    if (i < n && j < m) {
+      const size_t o = (size_t)i * m + j;
+      tv[r][tx] = P.V[o];
+      tl[r][tx] = P.Ll[o];
+      t1[r][tx] = P.Lu1i[o];
+      t2[r][tx] = P.Lu2[o];
+      t3[r][tx] = P.Lu3[o];
+      tsw[r][tx] = P.Lsw[o];
+    }
   }
   __syncthreads();
-  for (int c = ty; c < 64; c += 4) {
-    const int j = j0 + c, i = i0 + tx;
+  for (int cc = ty; cc < 32; cc += 8) {
+    const int j = j0 + cc, i = i0 + tx;
     if (i < n && j < m) {
-      const double sc = P.pos[j] == 0 ? 1.0 / P.nrm[j] : 1.0;
-      P.Z[(size_t)j * P.ldz + i] = tile[tx][c] * sc;
+      const int pj = P.pos[j];
+      const double sc = pj == 0 ? 1.0 / P.nrm[j] : 1.0;
+      P.Z[(size_t)j * P.ldz + i] = tv[tx][cc] * sc;
+      if (pj > 0) {
+        double4 rec;
+        rec.x = tl[tx][cc];
+        rec.y = t1[tx][cc];
+        rec.z = t2[tx][cc];
+        rec.w = t3[tx][cc];
+        reinterpret_cast<double4 *>(P.Lrec)[(size_t)j * n + i] = rec;
+        P.Lswb[(size_t)j * n + i] = tsw[tx][cc];
+      }
     }
   }
 }
 
 hipError_t launch_transpose(const Prob *probs, int nprob, int nmax, int mmax, hipStream_t s) {
   if (nprob <= 0 || nmax <= 0 || mmax <= 0) return hipSuccess;
-  dim3 grid((mmax + 63) / 64, (nmax + 63) / 64, nprob);
+  dim3 grid((mmax + 31) / 32, (nmax + 31) / 32, nprob);
   hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, probs);
   return hipGetLastError();
 }
@@ -409,18 +431,19 @@ hipError_t launch_transpose(const Prob *probs, int nprob, int nmax, int mmax, hi
 // A group of G workgroups (G = 1 for the small kernel) runs the members
 // c = 1..M-1 of the cluster in order; member c runs `iters` steps, each a
 // compact-WY orthogonalization of its current iterate v followed, except
-// after the last step, by the solve of Eq. (1).  Y (n x M, column l holds
-// y_{l}: zero above row l, never read there) and T (M x M upper triangular)
-// live in HBM; the phases of one step are separated by group barriers:
+// after the last step, by the solve of Eq. (1).  Y (n x M; column l holds
+// y_l, zero above row l and never read there) and T (M x M upper triangular)
+// are kept in HBM twice, column-major and row-major, so that every pass below
+// is a set of contiguous dot products, one wavefront per dot product:
 //
-//  P1  x   = Y_c^T v                (L^T v_chk + Yhat^T v_hat, column dots)
-//  P2  x'  = T_c^T x                (column dots over the upper triangle)
-//  P3  u   = v_hat - Yhat_c x'      (rows c..n-1, row tiles) and ||u||^2
+//  P1  x   = Y_c^T v                (L^T v_chk + Yhat^T v_hat; columns of Y)
+//  P2  x'  = T_c^T x                (columns of T)
+//  P3  u   = v_hat - Yhat_c x'      (rows c..n-1 of Y) and ||u||^2
 //  P4  c_j = -sgn(u_c)||u||, t_j = 1/(c_j^2 - u_c c_j), y_hat = u with
-//      u_c - c_j at row c; s = Yhat_c^T y_hat (column dots); column c of Y
+//      u_c - c_j at row c; s = Yhat_c^T y_hat (columns of Y); column c of Y
 //  P5  t_hat = -t_j T_c s and x'' = T_{c+1} r, r = row c of Y_{c+1}
-//      (one pass over T_c for both vectors); column c of T
-//  P6  q = Y_{c+1} x'' - e_c        (rows 0..n-1, row tiles)
+//      (rows of T, both vectors in one pass); column c of T
+//  P6  q = Y_{c+1} x'' - e_c        (rows of Y)
 //  P7  v = (T - lambda I)^{-1} q/||q||  (rank-0 workgroup)
 //
 // The product in P5 uses T_{c+1}; the transposed factor printed for this
@@ -429,34 +452,41 @@ hipError_t launch_transpose(const Prob *probs, int nprob, int nmax, int mmax, hi
 
 struct Ctx {
   int rank, size;      // workgroup rank in the group, group size (WGs)
-  unsigned *bar;       // group barrier counter (unused when size == 1)
-  unsigned target;     // counter value that ends the next barrier
+  unsigned *cnt;       // group arrival counter (unused when size == 1)
+  unsigned *flag;      // group release flag: last completed generation
+  unsigned gen;        // generation of the next barrier
   int *abort_flag;
   int gw, nw;          // wave index in the group, waves in the group
   int wave, lane;
 };
 
-constexpr unsigned long long kSpinLimit = 1ull << 22;  // ~seconds: only a broken run waits that long
+constexpr unsigned long long kSpinLimit = 1ull << 24;  // only a broken run waits that long
 
-// Group barrier.  Returns false (for every thread of the WG) when the run was
-// aborted, so callers unwind; a barrier that times out sets the abort flag.
+// Group barrier: arrive on the counter; the last arrival publishes the
+// generation on the flag; the others poll the flag.  Returns false (in every
+// thread of the WG) when the run was aborted; a wait that exceeds the spin
+// limit sets the abort flag, so every workgroup of every group unwinds.
+template <int NT>
 __device__ bool grp_sync(Ctx &c) {
   __syncthreads();
   if (c.size == 1) return true;
   __shared__ int s_ok;
-  c.target += (unsigned)c.size;
+  c.gen++;
   if (threadIdx.x == 0) {
     int ok = 1;
-    __atomic_thread_fence(__ATOMIC_RELEASE);
-    __hip_atomic_fetch_add(c.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned old = __hip_atomic_fetch_add(c.cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1u == c.gen * (unsigned)c.size)
+      __hip_atomic_store(c.flag, c.gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long spins = 0;
-    while (__hip_atomic_load(c.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < c.target) {
-      if (__hip_atomic_load(c.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins > kSpinLimit) {
-        __hip_atomic_store(c.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
+    while (__hip_atomic_load(c.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < c.gen) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 255ull) == 0) {
+        if (__hip_atomic_load(c.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+        if (spins > kSpinLimit) {
+          __hip_atomic_store(c.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
       }
     }
     __atomic_thread_fence(__ATOMIC_ACQUIRE);
@@ -466,126 +496,150 @@ __device__ bool grp_sync(Ctx &c) {
   return s_ok != 0;
 }
 
-// Scratch layout of one chain slot.
+// Scratch layout of one chain slot.  Vectors paired in dot products with
+// rows of Y or T (x, x', s, r, x'') start at the parity of the cluster start,
+// so both operands of every dot product have the same 16-byte alignment.
 struct Scr {
-  double *v, *q, *u, *P, *Q;       // n each
-  double *x, *xp, *s, *r, *xpp;    // mmax + 1 each
-  double *carry;                   // 2 (n / 64) + 8: chunk summaries, then carries
+  double *v, *q, *u, *P, *Q;       // n each (even offsets)
+  double *x, *xp, *s, *r, *xpp;    // mmax + 2 each (offset by the start parity)
+  double *carry;                   // n / 64 + 8: carries into the scan chunks
+  double *csum;                    // 2 (n / 64) + 16: chunk summaries (A, B)
   double *red;                     // nwg + 8
 };
 
+__host__ __device__ inline size_t even_up(size_t x) { return (x + 1) & ~(size_t)1; }
+
 __host__ __device__ inline size_t scr_doubles(int nmax, int mmax, int nwg) {
-  return 5 * (size_t)nmax + 5 * ((size_t)mmax + 1) + (2 * ((size_t)nmax / 64) + 8) + (size_t)nwg + 8 + 64;
+  return even_up(5 * even_up((size_t)nmax) + 5 * even_up((size_t)mmax + 2) +
+                 even_up((size_t)nmax / 64 + 8) + even_up(2 * ((size_t)nmax / 64) + 16) +
+                 (size_t)nwg + 8 + 64);
 }
 
 size_t chain_scratch_doubles(int nmax, int mmax, int nwg_in_group) {
   return scr_doubles(nmax, mmax, nwg_in_group);
 }
 
-__device__ inline Scr make_scr(double *base, int nmax, int mmax) {
+__device__ inline Scr make_scr(double *base, int nmax, int mmax, int parity) {
   Scr S;
   double *p = base;
-  S.v = p; p += nmax;
-  S.q = p; p += nmax;
-  S.u = p; p += nmax;
-  S.P = p; p += nmax;
-  S.Q = p; p += nmax;
-  S.x = p; p += mmax + 1;
-  S.xp = p; p += mmax + 1;
-  S.s = p; p += mmax + 1;
-  S.r = p; p += mmax + 1;
-  S.xpp = p; p += mmax + 1;
-  S.carry = p; p += 2 * (nmax / 64) + 8;
+  const size_t nn = even_up((size_t)nmax), mm = even_up((size_t)mmax + 2);
+  S.v = p; p += nn;
+  S.q = p; p += nn;
+  S.u = p; p += nn;
+  S.P = p; p += nn;
+  S.Q = p; p += nn;
+  S.x = p + parity; p += mm;
+  S.xp = p + parity; p += mm;
+  S.s = p + parity; p += mm;
+  S.r = p + parity; p += mm;
+  S.xpp = p + parity; p += mm;
+  S.carry = p; p += even_up((size_t)nmax / 64 + 8);
+  S.csum = p; p += even_up(2 * ((size_t)nmax / 64) + 16);
   S.red = p;
   return S;
 }
 
-// Dot product of a[lo..hi) and b[lo..hi) by one wave (four independent
-// accumulators per lane, fixed combination order).
+// Dot product of a[lo..hi) and b[lo..hi) by one wave: 16-byte loads, eight
+// in flight per lane, fixed combination order; every lane gets the sum.
+// a + lo and b + lo must have the same alignment modulo 16 bytes.
 __device__ __forceinline__ double wave_dot(const double *__restrict__ a, const double *__restrict__ b,
                                            int lo, int hi, int lane) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int i = lo + lane;
-  for (; i + 3 * kWave < hi; i += 4 * kWave) {
-    a0 = fma(a[i], b[i], a0);
-    a1 = fma(a[i + kWave], b[i + kWave], a1);
-    a2 = fma(a[i + 2 * kWave], b[i + 2 * kWave], a2);
-    a3 = fma(a[i + 3 * kWave], b[i + 3 * kWave], a3);
+  if (lo < hi && (reinterpret_cast<uintptr_t>(a + lo) & 15)) {
+    if (lane == 0) a0 = a[lo] * b[lo];
+    lo++;
   }
-  for (; i < hi; i += kWave) a0 = fma(a[i], b[i], a0);
+  const int np = (hi - lo) >> 1;
+  const double2 *__restrict__ A2 = reinterpret_cast<const double2 *>(a + lo);
+  const double2 *__restrict__ B2 = reinterpret_cast<const double2 *>(b + lo);
+  int p = lane;
+  for (; p + 3 * kWave < np; p += 4 * kWave) {
+    const double2 x0 = A2[p], x1 = A2[p + kWave], x2 = A2[p + 2 * kWave], x3 = A2[p + 3 * kWave];
+    const double2 y0 = B2[p], y1 = B2[p + kWave], y2 = B2[p + 2 * kWave], y3 = B2[p + 3 * kWave];
+    a0 = fma(x0.x, y0.x, a0); a0 = fma(x0.y, y0.y, a0);
+    a1 = fma(x1.x, y1.x, a1); a1 = fma(x1.y, y1.y, a1);
+    a2 = fma(x2.x, y2.x, a2); a2 = fma(x2.y, y2.y, a2);
+    a3 = fma(x3.x, y3.x, a3); a3 = fma(x3.y, y3.y, a3);
+  }
+  for (; p < np; p += kWave) {
+    const double2 x0 = A2[p], y0 = B2[p];
+    a0 = fma(x0.x, y0.x, a0); a0 = fma(x0.y, y0.y, a0);
+  }
+  if (((hi - lo) & 1) && lane == 0) a1 = fma(a[hi - 1], b[hi - 1], a1);
   return wave_sum((a0 + a1) + (a2 + a3));
 }
 
-// Row-tile product over a column-major matrix M (ld ldm): for 16 rows
-// [i0, i0+16) and 4 column phases per wave, acc(i) = sum_l M[i + l ld] x[l]
-// over l in [l0, l1) with the per-row predicate lo(i) <= l <= hi(i).
-// Returns the full sum in every lane of row i (lanes i%16, +16, +32, +48).
-template <int MODE>  // 0: no predicate, 1: l <= i (lower), 2: l >= i (upper)
-__device__ __forceinline__ double tile_rowdot(const double *__restrict__ Mx, size_t ldm,
-                                              const double *__restrict__ x, int i, bool row_ok,
-                                              int l0, int l1, int cp) {
-  double a0 = 0.0, a1 = 0.0;
-  if (row_ok) {
-    int l = l0 + cp;
-    for (; l + 4 < l1; l += 8) {
-      double m0 = Mx[(size_t)i + (size_t)l * ldm];
-      double m1 = Mx[(size_t)i + (size_t)(l + 4) * ldm];
-      if (MODE == 1) { if (l > i) m0 = 0.0; if (l + 4 > i) m1 = 0.0; }
-      if (MODE == 2) { if (l < i) m0 = 0.0; if (l + 4 < i) m1 = 0.0; }
-      a0 = fma(m0, x[l], a0);
-      a1 = fma(m1, x[l + 4], a1);
-    }
-    for (; l < l1; l += 4) {
-      double m0 = Mx[(size_t)i + (size_t)l * ldm];
-      if (MODE == 1 && l > i) m0 = 0.0;
-      if (MODE == 2 && l < i) m0 = 0.0;
-      a0 = fma(m0, x[l], a0);
-    }
+// Two dot products sharing the matrix row a: (a.b, a.c) over [0, len); a, b
+// and c must have the same alignment modulo 16 bytes.
+__device__ __forceinline__ void wave_dot2(const double *__restrict__ a, const double *__restrict__ b,
+                                          const double *__restrict__ c, int len, int lane,
+                                          double &ob, double &oc) {
+  double b0 = 0.0, b1 = 0.0, c0 = 0.0, c1 = 0.0;
+  int lo = 0;
+  if (len > 0 && (reinterpret_cast<uintptr_t>(a) & 15)) {
+    if (lane == 0) { b0 = a[0] * b[0]; c0 = a[0] * c[0]; }
+    lo = 1;
   }
-  double acc = a0 + a1;
-  acc += __shfl_xor(acc, 16, kWave);
-  acc += __shfl_xor(acc, 32, kWave);
-  return acc;
+  const int np = (len - lo) >> 1;
+  const double2 *__restrict__ A2 = reinterpret_cast<const double2 *>(a + lo);
+  const double2 *__restrict__ B2 = reinterpret_cast<const double2 *>(b + lo);
+  const double2 *__restrict__ C2 = reinterpret_cast<const double2 *>(c + lo);
+  int p = lane;
+  for (; p + kWave < np; p += 2 * kWave) {
+    const double2 m0 = A2[p], m1 = A2[p + kWave];
+    const double2 y0 = B2[p], y1 = B2[p + kWave];
+    const double2 z0 = C2[p], z1 = C2[p + kWave];
+    b0 = fma(m0.x, y0.x, b0); b0 = fma(m0.y, y0.y, b0);
+    c0 = fma(m0.x, z0.x, c0); c0 = fma(m0.y, z0.y, c0);
+    b1 = fma(m1.x, y1.x, b1); b1 = fma(m1.y, y1.y, b1);
+    c1 = fma(m1.x, z1.x, c1); c1 = fma(m1.y, z1.y, c1);
+  }
+  for (; p < np; p += kWave) {
+    const double2 m0 = A2[p], y0 = B2[p], z0 = C2[p];
+    b0 = fma(m0.x, y0.x, b0); b0 = fma(m0.y, y0.y, b0);
+    c0 = fma(m0.x, z0.x, c0); c0 = fma(m0.y, z0.y, c0);
+  }
+  if (((len - lo) & 1) && lane == 0) {
+    b1 = fma(a[len - 1], b[len - 1], b1);
+    c1 = fma(a[len - 1], c[len - 1], c1);
+  }
+  ob = wave_sum(b0 + b1);
+  oc = wave_sum(c0 + c1);
 }
 
-// Two vectors through one pass (P5).
-__device__ __forceinline__ void tile_rowdot2_upper(const double *__restrict__ Mx, size_t ldm,
-                                                   const double *__restrict__ x,
-                                                   const double *__restrict__ y, int i,
-                                                   bool row_ok, int l0, int l1, int cp,
-                                                   double &ox, double &oy) {
-  double ax = 0.0, ay = 0.0;
-  if (row_ok) {
-    for (int l = l0 + cp; l < l1; l += 4) {
-      double mv = Mx[(size_t)i + (size_t)l * ldm];
-      if (l < i) mv = 0.0;
-      ax = fma(mv, x[l], ax);
-      ay = fma(mv, y[l], ay);
-    }
-  }
-  ax += __shfl_xor(ax, 16, kWave);
-  ax += __shfl_xor(ax, 32, kWave);
-  ay += __shfl_xor(ay, 16, kWave);
-  ay += __shfl_xor(ay, 32, kWave);
-  ox = ax;
-  oy = ay;
+// Folded assignment of `cnt` dot products whose lengths grow (or shrink)
+// linearly with their index: indices p and cnt - 1 - p form pair p, pairs go
+// round-robin to the waves, so every wave's total length is about the same.
+// Task t of wave gw is pair gw + (t / 2) nw, its front index for even t and
+// its back index for odd t.
+__device__ __forceinline__ int fold_index(int gw, int nw, int t, int cnt) {
+  const int p = gw + (t >> 1) * nw;
+  return (t & 1) ? cnt - 1 - p : p;
+}
+
+__device__ __forceinline__ bool fold_valid(int gw, int nw, int t, int cnt) {
+  const int p = gw + (t >> 1) * nw;
+  if (2 * p >= cnt) return false;
+  return (t & 1) ? (cnt - 1 - p > p) : true;
 }
 
 // Sum over the group of per-lane partials `part`: WG partial to red[rank],
 // barrier, then every WG sums red[0..size) in the same fixed order.
 // Returns false on abort.
+template <int NT>
 __device__ bool grp_sum(Ctx &c, double part, double *red, double &out) {
-  __shared__ double s_w[kChainWaves];
+  constexpr int NW = NT / kWave;
+  __shared__ double s_w[NW];
   __shared__ double s_tot;
   part = wave_sum(part);
   if (c.lane == 0) s_w[c.wave] = part;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int q = 0; q < kChainWaves; q++) t += s_w[q];
+    for (int q = 0; q < NW; q++) t += s_w[q];
     red[c.rank] = t;
   }
-  if (!grp_sync(c)) return false;
+  if (!grp_sync<NT>(c)) return false;
   if (c.wave == 0) {
     double t = 0.0;
     for (int r = c.lane; r < c.size; r += kWave) t += red[r];
@@ -598,55 +652,52 @@ __device__ bool grp_sum(Ctx &c, double part, double *red, double &out) {
 }
 
 struct CView {
-  int n, m, M, s0;
-  double *Y;            // column l at Y + l * n
-  double *T;            // T[p, l] at T[p + l * ldt]
-  size_t ldt;
+  int n, M;
+  double *Y;            // column-major: cluster column l at Y + l * ldy
+  double *Yr;           // row-major:    cluster row i at Yr + i * ldm
+  double *T;            // column-major: T[p, l] at T[p + l * ldm]
+  double *Tr;           // row-major:    T[p, l] at Tr[p * ldm + l]
+  size_t ldy, ldm;
   double *Z;            // column-major, ldz
   size_t ldz;
-  const double *W;
-  const double *Ll, *Lu1i, *Lu2, *Lu3;   // + s0: member c at offset c, stride m
-  const unsigned char *Lsw;
+  const double4 *Lrec;  // member c's LU rows at Lrec + c * n
+  const unsigned char *Lswb;
 };
 
-// Solve (T - lambda I) v = q/||q|| with the stored LU of member c; run by one
-// whole workgroup.  The forward sweep is a scan of the affine maps
-// cur_{i+1} = A_i cur_i + B_i (|A_i| <= 1 under partial pivoting, so the
-// scan is as stable as the recurrence); the back sweep is sequential in wave 0.
-__device__ void wg_solve(const CView &cv, int c, const double *__restrict__ q, double *__restrict__ v,
-                         const Scr &S, int wave, int lane) {
+// Solve (T - lambda I) v = q/||q|| with the stored LU of member c, spread over
+// the whole group.  rn = 1/||q|| comes from the pass that produced q.
+//  S1  every wave scans 64-row chunks of the affine maps
+//      cur_{i+1} = A_i cur_i + B_i of the forward sweep (|A_i| <= 1 under
+//      partial pivoting, so the scan is as stable as the recurrence);
+//  S2  every workgroup scans the chunk summaries for the carries into each
+//      chunk (in LDS) and forms y'_i = y_i / u1_i for its own rows;
+//  S3  the back sweep x_i = y'_i - (u2/u1)_i x_{i+1} - (u3/u1)_i x_{i+2}
+//      runs sequentially in wave 0 of rank 0 (a blocked version of it is not
+//      stable), 64 rows per staged block with two blocks in flight.
+// Returns false on abort.
+constexpr int kLdsCarries = 2048;
+
+template <int NT>
+__device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restrict__ q,
+                          double *__restrict__ v, const Scr &S, double rn) {
   const int n = cv.n;
-  const size_t m = (size_t)cv.m;
-  const int tid = threadIdx.x;
-  const double *__restrict__ Ll = cv.Ll + c;
-  const double *__restrict__ U1 = cv.Lu1i + c;
-  const double *__restrict__ U2 = cv.Lu2 + c;
-  const double *__restrict__ U3 = cv.Lu3 + c;
-  const unsigned char *__restrict__ SW = cv.Lsw + c;
-  __shared__ double s_w[kChainWaves];
-  __shared__ double s_rn;
+  const int tid = threadIdx.x, lane = cx.lane, wave = cx.wave;
+  const int gtid = cx.rank * NT + tid, gthreads = cx.size * NT;
+  const double4 *__restrict__ R = cv.Lrec + (size_t)c * n;
+  const unsigned char *__restrict__ SW = cv.Lswb + (size_t)c * n;
+  __shared__ double s_carry[kLdsCarries + 1];
   __shared__ double st_u2[kWave], st_u3[kWave], st_y[kWave], st_x[kWave];
 
-  // 1/||q||
-  double ss = 0.0;
-  for (int i = tid; i < n; i += kChainThreads) ss = fma(q[i], q[i], ss);
-  ss = wave_sum(ss);
-  if (lane == 0) s_w[wave] = ss;
-  __syncthreads();
-  if (tid == 0) s_rn = 1.0 / sqrt((s_w[0] + s_w[1]) + (s_w[2] + s_w[3]));
-  __syncthreads();
-  const double rn = s_rn;
-
-  // forward maps for rows 0..n-2, scanned in chunks of 64
+  // S1: chunk scans
   const int nmaps = n - 1;
   const int nch = (nmaps + kWave - 1) / kWave;
-  for (int k = wave; k < nch; k += kChainWaves) {
+  for (int k = cx.gw; k < nch; k += cx.nw) {
     const int i = k * kWave + lane;
     double A = 1.0, B = 0.0;
     if (i < nmaps) {
       const double bn = q[i + 1] * rn;
-      const double l = Ll[(size_t)i * m];
-      if (SW[(size_t)i * m]) { A = 1.0; B = -(l * bn); }
+      const double l = R[i].x;
+      if (SW[i]) { A = 1.0; B = -(l * bn); }
       else { A = -l; B = bn; }
     }
 #pragma unroll
@@ -656,55 +707,95 @@ __device__ void wg_solve(const CView &cv, int c, const double *__restrict__ q, d
       if (lane >= off) { B = fma(A, Bp, B); A = A * Ap; }
     }
     if (i < nmaps) { S.P[i] = A; S.Q[i] = B; }
-    if (lane == kWave - 1) { S.carry[2 * k] = A; S.carry[2 * k + 1] = B; }
+    if (lane == kWave - 1) { S.csum[2 * k] = A; S.csum[2 * k + 1] = B; }
   }
-  __syncthreads();
-  if (tid == 0) {
-    // carries into each chunk: cur_{64k}; stored over the chunk summaries
+  if (!grp_sync<NT>(cx)) return false;
+
+  // S2: carries into each chunk (scan of the chunk summaries, 64 at a time)
+  const bool in_lds = nch <= kLdsCarries;
+  if (in_lds ? (wave == 0) : (cx.rank == 0 && wave == 0)) {
     double cur = q[0] * rn;
-    for (int k = 0; k < nch; k++) {
-      const double A = S.carry[2 * k], B = S.carry[2 * k + 1];
-      S.carry[2 * k] = cur;
-      cur = fma(A, cur, B);
+    for (int k0 = 0; k0 < nch; k0 += kWave) {
+      const int k = k0 + lane;
+      double A = 1.0, B = 0.0;
+      if (k < nch) { A = S.csum[2 * k]; B = S.csum[2 * k + 1]; }
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const double Ap = __shfl_up(A, off, kWave);
+        const double Bp = __shfl_up(B, off, kWave);
+        if (lane >= off) { B = fma(A, Bp, B); A = A * Ap; }
+      }
+      const double Ae = __shfl_up(A, 1, kWave), Be = __shfl_up(B, 1, kWave);
+      const double ck = lane == 0 ? cur : fma(Ae, cur, Be);
+      if (k < nch) {
+        if (in_lds) s_carry[k] = ck;
+        else S.carry[k] = ck;
+      }
+      const double Al = __shfl(A, kWave - 1, kWave), Bl = __shfl(B, kWave - 1, kWave);
+      cur = fma(Al, cur, Bl);
     }
-    S.carry[2 * nch] = cur;
+    if (lane == 0) {
+      if (in_lds) s_carry[nch] = cur;
+      else S.carry[nch] = cur;
+    }
   }
-  __syncthreads();
-  for (int i = tid; i < n; i += kChainThreads) {
+  if (in_lds) {
+    __syncthreads();
+  } else if (!grp_sync<NT>(cx)) {
+    return false;
+  }
+  const double *carry = in_lds ? s_carry : S.carry;
+  for (int i = gtid; i < n; i += gthreads) {
     const int k = i / kWave;
-    const double ck = S.carry[2 * k];
+    const double ck = carry[k];
     const double cur = (i % kWave == 0) ? ck : fma(S.P[i - 1], ck, S.Q[i - 1]);
     double y = cur;
-    if (i < nmaps && SW[(size_t)i * m]) y = q[i + 1] * rn;
-    v[i] = y * U1[(size_t)i * m];
+    if (i < nmaps && SW[i]) y = q[i + 1] * rn;
+    v[i] = y * R[i].y;
   }
-  __syncthreads();
+  if (!grp_sync<NT>(cx)) return false;
 
-  // back substitution, sequential in wave 0, 64 rows per staged block
-  if (wave == 0) {
+  // S3: back substitution
+  if (cx.rank == 0 && wave == 0) {
     double x1 = 0.0, x2 = 0.0;
     int hi = n;
     int lo = hi - kWave > 0 ? hi - kWave : 0;
-    double pu2 = 0.0, pu3 = 0.0, py = 0.0;
+    int lo1 = lo - kWave > 0 ? lo - kWave : 0;
+    double pu2 = 0.0, pu3 = 0.0, py = 0.0, qu2 = 0.0, qu3 = 0.0, qy = 0.0;
     if (lo + lane < hi) {
-      const size_t o = (size_t)(lo + lane) * m;
-      pu2 = U2[o]; pu3 = U3[o]; py = v[lo + lane];
+      const double4 r = R[lo + lane];
+      pu2 = r.z; pu3 = r.w; py = v[lo + lane];
+    }
+    if (lo > 0 && lo1 + lane < lo) {
+      const double4 r = R[lo1 + lane];
+      qu2 = r.z; qu3 = r.w; qy = v[lo1 + lane];
     }
     while (hi > 0) {
       st_u2[lane] = pu2; st_u3[lane] = pu3; st_y[lane] = py;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int nlo = lo - kWave > 0 ? lo - kWave : 0;
-      if (lo > 0 && nlo + lane < lo) {
-        const size_t o = (size_t)(nlo + lane) * m;
-        pu2 = U2[o]; pu3 = U3[o]; py = v[nlo + lane];
+      pu2 = qu2; pu3 = qu3; py = qy;
+      const int lo2 = lo1 - kWave > 0 ? lo1 - kWave : 0;
+      if (lo1 > 0 && lo2 + lane < lo1) {
+        const double4 r = R[lo2 + lane];
+        qu2 = r.z; qu3 = r.w; qy = v[lo2 + lane];
       }
-      for (int tt = hi - lo - 1; tt >= 0; tt--) {
-        const double x = fma(-st_u2[tt], x1, fma(-st_u3[tt], x2, st_y[tt]));
-        x2 = x1;
-        x1 = x;
-        if (lane == tt) st_x[tt] = x;
+      if (hi - lo == kWave) {
+#pragma unroll
+        for (int tt = kWave - 1; tt >= 0; tt--) {
+          const double x = fma(-st_u2[tt], x1, fma(-st_u3[tt], x2, st_y[tt]));
+          x2 = x1;
+          x1 = x;
+          st_x[tt] = x;
+        }
+      } else {
+        for (int tt = hi - lo - 1; tt >= 0; tt--) {
+          const double x = fma(-st_u2[tt], x1, fma(-st_u3[tt], x2, st_y[tt]));
+          x2 = x1;
+          x1 = x;
+          st_x[tt] = x;
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -712,79 +803,91 @@ __device__ void wg_solve(const CView &cv, int c, const double *__restrict__ q, d
       if (lo + lane < hi) v[lo + lane] = st_x[lane];
       __builtin_amdgcn_wave_barrier();
       hi = lo;
-      lo = nlo;
+      lo = lo1;
+      lo1 = lo2;
     }
   }
-  __syncthreads();
+  return grp_sync<NT>(cx);
 }
 
 // Runs the chain of one cluster with the group described by ctx.  Returns
 // false if the run was aborted.
+template <int NT>
 __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr &S, int iters) {
   CView cv;
-  cv.n = P.n; cv.m = P.m; cv.M = it.size; cv.s0 = it.start;
-  cv.Y = P.Y + (size_t)it.start * P.n;
-  cv.ldt = (size_t)P.m;
-  cv.T = P.T + (size_t)it.start + (size_t)it.start * cv.ldt;
-  cv.Z = P.Z + (size_t)it.start * P.ldz;
+  const size_t s0 = (size_t)it.start;
+  cv.n = P.n; cv.M = it.size;
+  cv.ldy = (size_t)P.ldy;
+  cv.ldm = (size_t)P.ldm;
+  cv.Y = P.Y + s0 * cv.ldy;
+  cv.Yr = P.Yr + s0;
+  cv.T = P.T + s0 + s0 * cv.ldm;
+  cv.Tr = P.Tr + s0 + s0 * cv.ldm;
+  cv.Z = P.Z + s0 * P.ldz;
   cv.ldz = (size_t)P.ldz;
-  cv.W = P.W + it.start;
-  cv.Ll = P.Ll + it.start; cv.Lu1i = P.Lu1i + it.start;
-  cv.Lu2 = P.Lu2 + it.start; cv.Lu3 = P.Lu3 + it.start;
-  cv.Lsw = P.Lsw + it.start;
+  cv.Lrec = reinterpret_cast<const double4 *>(P.Lrec) + s0 * P.n;
+  cv.Lswb = P.Lswb + s0 * P.n;
   const int n = cv.n;
+  const size_t ldy = cv.ldy, ldm = cv.ldm;
   const int tid = threadIdx.x, lane = cx.lane;
-  const int gtid = cx.rank * kChainThreads + tid, gthreads = cx.size * kChainThreads;
-  __shared__ double s_sc[4];
+  const int gtid = cx.rank * NT + tid, gthreads = cx.size * NT;
 
   // Y_1, T_1 from the first member's unit vector z (Alg. 4, first step of the
   // second member): c_1 = -sgn(z_0)||z||, y_1 = z - c_1 e_0, t_1 = 1/(c_1^2 - z_0 c_1).
+  // The raw first iterate of member 1 is staged into the aligned scratch v.
   {
     const double *z = cv.Z;
+    const double *z1 = cv.Z + cv.ldz;
     double part = 0.0;
-    for (int i = gtid; i < n; i += gthreads) part = fma(z[i], z[i], part);
+    for (int i = gtid; i < n; i += gthreads) {
+      part = fma(z[i], z[i], part);
+      S.v[i] = z1[i];
+    }
     double nz2;
-    if (!grp_sum(cx, part, S.red, nz2)) return false;
+    if (!grp_sum<NT>(cx, part, S.red, nz2)) return false;
     const double z0 = z[0];
     const double g = -(z0 >= 0.0 ? 1.0 : -1.0) * sqrt(nz2);
-    for (int i = gtid; i < n; i += gthreads) cv.Y[i] = (i == 0) ? z0 - g : z[i];
-    if (gtid == 0) cv.T[0] = (g == 0.0) ? 0.0 : 1.0 / (g * g - z0 * g);
-    if (!grp_sync(cx)) return false;
+    for (int i = gtid; i < n; i += gthreads) {
+      const double y = (i == 0) ? z0 - g : z[i];
+      cv.Y[i] = y;
+      cv.Yr[(size_t)i * ldm] = y;
+    }
+    if (gtid == 0) {
+      const double t = (g == 0.0) ? 0.0 : 1.0 / (g * g - z0 * g);
+      cv.T[0] = t;
+      cv.Tr[0] = t;
+    }
+    if (!grp_sync<NT>(cx)) return false;
   }
 
+  const double *vin = S.v;
   for (int c = 1; c < cv.M; c++) {
-    const double *vin = cv.Z + (size_t)c * cv.ldz;   // raw first-iteration solve
     for (int k = 1; k <= iters; k++) {
       // P1: x = Y_c^T v
       for (int l = cx.gw; l < c; l += cx.nw) {
-        const double acc = wave_dot(cv.Y + (size_t)l * n, vin, l, n, lane);
+        const double acc = wave_dot(cv.Y + (size_t)l * ldy, vin, l, n, lane);
         if (lane == 0) S.x[l] = acc;
       }
-      if (!grp_sync(cx)) return false;
-      // P2: x' = T_c^T x
-      for (int l = cx.gw; l < c; l += cx.nw) {
-        const double acc = wave_dot(cv.T + (size_t)l * cv.ldt, S.x, 0, l + 1, lane);
+      if (!grp_sync<NT>(cx)) return false;
+      // P2: x' = T_c^T x (column l has l + 1 entries: folded assignment)
+      for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
+        const int l = fold_index(cx.gw, cx.nw, t, c);
+        const double acc = wave_dot(cv.T + (size_t)l * ldm, S.x, 0, l + 1, lane);
         if (lane == 0) S.xp[l] = acc;
       }
-      if (!grp_sync(cx)) return false;
+      if (!grp_sync<NT>(cx)) return false;
       // P3: u = v_hat - Yhat_c x' over rows c..n-1, and ||u||^2
       double part = 0.0;
-      {
-        const int nt = (n - c + 15) / 16;
-        const int rr = lane & 15, cp = lane >> 4;
-        for (int t = cx.gw; t < nt; t += cx.nw) {
-          const int i = c + t * 16 + rr;
-          const bool ok = i < n;
-          const double acc = tile_rowdot<0>(cv.Y, (size_t)n, S.xp, i, ok, 0, c, cp);
-          if (ok && cp == 0) {
-            const double ui = vin[i] - acc;
-            S.u[i] = ui;
-            part = fma(ui, ui, part);
-          }
+      for (int i = c + cx.gw; i < n; i += cx.nw) {
+        const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xp, 0, c, lane);
+        const double ui = vin[i] - acc;
+        if (lane == 0) {
+          S.u[i] = ui;
+          part = fma(ui, ui, part);
         }
       }
       double beta2;
-      if (!grp_sum(cx, part, S.red, beta2)) return false;
+      if (!grp_sum<NT>(cx, part, S.red, beta2)) return false;
       // P4: Householder vector and s = Yhat_c^T y_hat
       const double alpha = S.u[c];
       const double beta = sqrt(beta2);
@@ -792,8 +895,8 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
       const double tj = (gam == 0.0) ? 0.0 : 1.0 / (gam * gam - alpha * gam);
       const double yc = alpha - gam;
       for (int l = cx.gw; l < c; l += cx.nw) {
-        const double *col = cv.Y + (size_t)l * n;
-        double acc = wave_dot(col, S.u, c + 1, n, lane);
+        const double *col = cv.Y + (size_t)l * ldy;
+        const double acc = wave_dot(col, S.u, c + 1, n, lane);
         if (lane == 0) {
           const double rl = col[c];
           S.s[l] = fma(rl, yc, acc);
@@ -801,66 +904,80 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         }
       }
       {
-        double *ycol = cv.Y + (size_t)c * n;
-        for (int i = c + gtid; i < n; i += gthreads) ycol[i] = (i == c) ? yc : S.u[i];
-        if (gtid == 0) cv.T[(size_t)c + (size_t)c * cv.ldt] = tj;
+        double *ycol = cv.Y + (size_t)c * ldy;
+        for (int i = c + gtid; i < n; i += gthreads) {
+          const double y = (i == c) ? yc : S.u[i];
+          ycol[i] = y;
+          cv.Yr[(size_t)i * ldm + c] = y;
+        }
+        if (gtid == 0) {
+          cv.T[(size_t)c + (size_t)c * ldm] = tj;
+          cv.Tr[(size_t)c * ldm + c] = tj;
+        }
       }
-      if (!grp_sync(cx)) return false;
+      if (!grp_sync<NT>(cx)) return false;
       // P5: t_hat = -t_j T_c s (column c of T) and x'' = T_{c+1} r
-      {
-        const int nt = (c + 15) / 16;
-        const int rr = lane & 15, cp = lane >> 4;
-        for (int t = cx.gw; t < nt; t += cx.nw) {
-          const int p = t * 16 + rr;
-          const bool ok = p < c;
-          double ts, tr;
-          tile_rowdot2_upper(cv.T, cv.ldt, S.s, S.r, p, ok, t * 16, c, cp, ts, tr);
-          if (ok && cp == 0) {
-            const double th = -tj * ts;
-            cv.T[(size_t)p + (size_t)c * cv.ldt] = th;
-            S.xpp[p] = fma(th, yc, tr);
-          }
-        }
-        if (gtid == 0) S.xpp[c] = tj * yc;
-      }
-      if (!grp_sync(cx)) return false;
-      // P6: q = Y_{c+1} x'' - e_c
-      double *qout = (k == iters) ? (cv.Z + (size_t)c * cv.ldz) : S.q;
-      {
-        const int nt = (n + 15) / 16;
-        const int rr = lane & 15, cp = lane >> 4;
-        for (int t = cx.gw; t < nt; t += cx.nw) {
-          const int i0 = t * 16;
-          const int i = i0 + rr;
-          const bool ok = i < n;
-          const int l1 = (i0 + 15 < c ? i0 + 15 : c) + 1;
-          const double acc = tile_rowdot<1>(cv.Y, (size_t)n, S.xpp, i, ok, 0, l1, cp);
-          if (ok && cp == 0) qout[i] = (i == c) ? acc - 1.0 : acc;
+      // (row p has c - p entries: folded assignment)
+      for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
+        const int p = fold_index(cx.gw, cx.nw, t, c);
+        double ts, tr;
+        wave_dot2(cv.Tr + (size_t)p * ldm + p, S.s + p, S.r + p, c - p, lane, ts, tr);
+        if (lane == 0) {
+          const double th = -tj * ts;
+          cv.T[(size_t)p + (size_t)c * ldm] = th;
+          cv.Tr[(size_t)p * ldm + c] = th;
+          S.xpp[p] = fma(th, yc, tr);
         }
       }
-      if (!grp_sync(cx)) return false;
-      if (k < iters) {
-        // P7: next iterate
-        if (cx.rank == 0) wg_solve(cv, c, S.q, S.v, S, cx.wave, lane);
-        if (!grp_sync(cx)) return false;
-        vin = S.v;
+      if (gtid == 0) S.xpp[c] = tj * yc;
+      if (!grp_sync<NT>(cx)) return false;
+      // P6: q = Y_{c+1} x'' - e_c; after the last step, also stage the next
+      // member's raw first iterate into the aligned scratch v.  Rows below c
+      // are shorter (min(i, c) + 1 entries): folded assignment.
+      const bool last = (k == iters);
+      double *qout = last ? (cv.Z + (size_t)c * cv.ldz) : S.q;
+      double qpart = 0.0;
+      for (int t = 0; fold_valid(cx.gw, cx.nw, t, n); t++) {
+        const int i = fold_index(cx.gw, cx.nw, t, n);
+        const int l1 = (i < c ? i : c) + 1;
+        const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xpp, 0, l1, lane);
+        const double qi = (i == c) ? acc - 1.0 : acc;
+        if (lane == 0) {
+          qout[i] = qi;
+          qpart = fma(qi, qi, qpart);
+        }
+      }
+      if (last) {
+        if (c + 1 < cv.M) {
+          const double *zn = cv.Z + (size_t)(c + 1) * cv.ldz;
+          for (int i = gtid; i < n; i += gthreads) S.v[i] = zn[i];
+        }
+        if (!grp_sync<NT>(cx)) return false;
+      } else {
+        // P7: next iterate v = (T - lambda I)^{-1} q / ||q||
+        double qn2;
+        if (!grp_sum<NT>(cx, qpart, S.red, qn2)) return false;
+        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(qn2))) return false;
       }
     }
   }
-  (void)s_sc;
   return true;
 }
 
+constexpr int kSmallThreads = 256;
+constexpr int kCoopThreads = 512;
+
 // Small clusters: one workgroup per cluster, items taken from a work counter.
-__global__ void __launch_bounds__(kChainThreads) k_chain_small(const Prob *__restrict__ probs,
+__global__ void __launch_bounds__(kSmallThreads) k_chain_small(const Prob *__restrict__ probs,
                                                                const ChainItem *__restrict__ items,
                                                                int nitems, int *counter,
                                                                ChainScratch scr, int iters) {
   __shared__ int s_item;
   Ctx cx;
-  cx.rank = 0; cx.size = 1; cx.bar = nullptr; cx.target = 0; cx.abort_flag = nullptr;
+  cx.rank = 0; cx.size = 1; cx.cnt = nullptr; cx.flag = nullptr; cx.gen = 0;
+  cx.abort_flag = nullptr;
   cx.wave = threadIdx.x / kWave; cx.lane = threadIdx.x % kWave;
-  cx.gw = cx.wave; cx.nw = kChainWaves;
+  cx.gw = cx.wave; cx.nw = kSmallThreads / kWave;
   double *base = scr.base + (size_t)blockIdx.x * scr.stride;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -870,47 +987,49 @@ __global__ void __launch_bounds__(kChainThreads) k_chain_small(const Prob *__res
     if (idx >= nitems) break;
     const ChainItem it = items[idx];
     const Prob &P = probs[it.prob];
-    const Scr S = make_scr(base, P.n, P.m);
-    run_chain(cx, P, it, S, iters);
+    const Scr S = make_scr(base, P.n, P.m, it.start & 1);
+    run_chain<kSmallThreads>(cx, P, it, S, iters);
   }
 }
 
 hipError_t launch_chain_small(const Prob *probs, const ChainItem *items, int nitems, int *counter,
                               ChainScratch scr, int nwg, int iters, hipStream_t s) {
   if (nitems <= 0 || nwg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_chain_small, dim3(nwg), dim3(kChainThreads), 0, s, probs, items, nitems,
+  hipLaunchKernelGGL(k_chain_small, dim3(nwg), dim3(kSmallThreads), 0, s, probs, items, nitems,
                      counter, scr, iters);
   return hipGetLastError();
 }
 
 // Large clusters: cooperative launch; workgroup w belongs to group
 // wg_group[w] and runs that group's items in order with group barriers.
-__global__ void __launch_bounds__(kChainThreads) k_chain_coop(const Prob *__restrict__ probs,
-                                                              const ChainItem *__restrict__ items,
-                                                              const Group *__restrict__ groups,
-                                                              const int *__restrict__ wg_group,
-                                                              unsigned *bars, int *abort_flag,
-                                                              ChainScratch scr, int iters) {
+// bars holds two counters per group, 64 bytes apart: arrivals, release flag.
+__global__ void __launch_bounds__(kCoopThreads) k_chain_coop(const Prob *__restrict__ probs,
+                                                             const ChainItem *__restrict__ items,
+                                                             const Group *__restrict__ groups,
+                                                             const int *__restrict__ wg_group,
+                                                             unsigned *bars, int *abort_flag,
+                                                             ChainScratch scr, int iters) {
   const int g = wg_group[blockIdx.x];
   if (g < 0) return;
   const Group G = groups[g];
   Ctx cx;
   cx.rank = (int)blockIdx.x - G.wg0;
   cx.size = G.nwg;
-  cx.bar = bars + g;
-  cx.target = 0;
+  cx.cnt = bars + (size_t)g * 32;
+  cx.flag = bars + (size_t)g * 32 + 16;
+  cx.gen = 0;
   cx.abort_flag = abort_flag;
   cx.wave = threadIdx.x / kWave;
   cx.lane = threadIdx.x % kWave;
-  cx.gw = cx.rank * kChainWaves + cx.wave;
-  cx.nw = cx.size * kChainWaves;
+  cx.gw = cx.rank * (kCoopThreads / kWave) + cx.wave;
+  cx.nw = cx.size * (kCoopThreads / kWave);
   double *base = scr.base + (size_t)g * scr.stride;
   for (int q = 0; q < G.nit; q++) {
     const ChainItem it = items[G.it0 + q];
     const Prob &P = probs[it.prob];
-    const Scr S = make_scr(base, P.n, P.m);
-    if (!run_chain(cx, P, it, S, iters)) return;
-    if (!grp_sync(cx)) return;   // scratch reuse across items
+    const Scr S = make_scr(base, P.n, P.m, it.start & 1);
+    if (!run_chain<kCoopThreads>(cx, P, it, S, iters)) return;
+    if (!grp_sync<kCoopThreads>(cx)) return;   // scratch reuse across items
   }
 }
 
@@ -920,18 +1039,22 @@ hipError_t launch_chain_coop(const Prob *probs, const ChainItem *items, const Gr
   if (nwg <= 0) return hipSuccess;
   void *args[] = {(void *)&probs, (void *)&items, (void *)&groups, (void *)&wg_group,
                   (void *)&bars, (void *)&abort_flag, (void *)&scr, (void *)&iters};
-  return hipLaunchCooperativeKernel((const void *)k_chain_coop, dim3(nwg), dim3(kChainThreads),
+  return hipLaunchCooperativeKernel((const void *)k_chain_coop, dim3(nwg), dim3(kCoopThreads),
                                     args, 0, s);
 }
 
+// One cooperative workgroup (8 waves, up to 256 VGPRs each) per compute unit
+// keeps the group barriers cheap (their cost grows with the number of
+// arriving workgroups) while 8 waves per CU with 8 KB of loads in flight
+// each still saturate HBM on the streaming passes.
 int coop_max_wgs(int device) {
   int ncu = 0, per = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain_coop,
-                                                   kChainThreads, 0) != hipSuccess)
+                                                   kCoopThreads, 0) != hipSuccess)
     return 0;
-  return ncu * per;
+  return per >= 1 ? ncu : 0;
 }
 
 int small_max_wgs(int device) {
@@ -939,7 +1062,7 @@ int small_max_wgs(int device) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain_small,
-                                                   kChainThreads, 0) != hipSuccess)
+                                                   kSmallThreads, 0) != hipSuccess)
     return 0;
   return ncu * per;
 }
