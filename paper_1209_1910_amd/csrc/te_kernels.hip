@@ -9,6 +9,7 @@
 #include <hip/hip_cooperative_groups.h>
 #include <float.h>
 #include <math.h>
+#include <stdlib.h>
 
 #include "te_internal.h"
 
@@ -1033,10 +1034,29 @@ __global__ void __launch_bounds__(kCoopThreads) k_chain_coop(const Prob *__restr
   }
 }
 
+// The chain kernel relies on all of its workgroups being resident at once
+// (one per CU, within the occupancy limit checked by coop_max_wgs); the
+// cooperative launch guarantees that.  TE_COOP_LAUNCH=0 in the environment
+// dispatches the same grid with a regular launch instead, for profilers that
+// cannot handle cooperative dispatches; a workgroup that were not resident
+// would time out in its first barrier and abort the run with TE_ERR_KERNEL.
+static bool coop_launch_enabled() {
+  static const bool on = [] {
+    const char *v = getenv("TE_COOP_LAUNCH");
+    return !(v && v[0] == '0' && v[1] == '\0');
+  }();
+  return on;
+}
+
 hipError_t launch_chain_coop(const Prob *probs, const ChainItem *items, const Group *groups,
                              const int *wg_group, unsigned *bars, int *abort_flag,
                              ChainScratch scr, int nwg, int iters, hipStream_t s) {
   if (nwg <= 0) return hipSuccess;
+  if (!coop_launch_enabled()) {
+    hipLaunchKernelGGL(k_chain_coop, dim3(nwg), dim3(kCoopThreads), 0, s, probs, items, groups,
+                       wg_group, bars, abort_flag, scr, iters);
+    return hipGetLastError();
+  }
   void *args[] = {(void *)&probs, (void *)&items, (void *)&groups, (void *)&wg_group,
                   (void *)&bars, (void *)&abort_flag, (void *)&scr, (void *)&iters};
   return hipLaunchCooperativeKernel((const void *)k_chain_coop, dim3(nwg), dim3(kCoopThreads),
