@@ -101,6 +101,86 @@ def cpu_baseline(n_sample: int, n_target: int):
     }
 
 
+def batched_bench(count: int, plain_count: int) -> int:
+    """Batched workload: `count` independent problems (n log-uniform in
+    [64, 2048], 25 % glued Wilkinson), all eigenpairs.  Times one batched call
+    against plain one-problem-per-call runs of the same problems."""
+    import numpy as np
+    import torch
+
+    from paper_1209_1910_amd import binding, inputs
+
+    probs = inputs.batched_problems(count=count, seed=1)
+    ns = np.array([len(d) for d, _, _ in probs], dtype=np.int64)
+    off = np.zeros(count + 1, dtype=np.int64)
+    off[1:] = np.cumsum(ns)
+    woff = off[:-1].copy()
+    zsz = ns * ns
+    zoff = np.zeros(count, dtype=np.int64)
+    zoff[1:] = np.cumsum(zsz)[:-1]
+    dev = torch.device("cuda:0")
+    d_all = torch.from_numpy(np.concatenate([d for d, _, _ in probs])).to(dev)
+    e_all = torch.from_numpy(np.concatenate([e for _, e, _ in probs if len(e)])).to(dev)
+    W_all = torch.empty(int(ns.sum()), dtype=torch.float64, device=dev)
+    Z_all = torch.empty(int(zsz.sum()), dtype=torch.float64, device=dev)
+    il = np.ones(count, dtype=np.int32)
+    iu = ns.astype(np.int32)
+    torch.cuda.synchronize()
+    print(f"[bench] batched: {count} problems, sum n = {int(ns.sum())}", file=sys.stderr, flush=True)
+    binding.tridiag_eigvecs_batched_raw(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff)
+    torch.cuda.synchronize()
+    print("[bench] batched warm-up done", file=sys.stderr, flush=True)
+    binding.te_timing_reset()
+    binding.te_timing_enable(True)
+    t0 = time.perf_counter()
+    binding.tridiag_eigvecs_batched_raw(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    binding.te_timing_enable(False)
+    phases = binding.te_timing_read()
+    print(f"[bench] batched call {t_batched:.3f} s", file=sys.stderr, flush=True)
+
+    # plain path: one tridiag_eigvecs call per problem on the same stream
+    pc = min(plain_count, count)
+    eoff = off[:-1] - np.arange(count)
+    worst = 0.0
+    t0 = time.perf_counter()
+    for b in range(pc):
+        n = int(ns[b])
+        W, Z = binding.tridiag_eigvecs(d_all[off[b]:off[b + 1]], e_all[eoff[b]:eoff[b] + n - 1])
+        if b % 512 == 511:
+            print(f"[bench] plain {b + 1}/{pc}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) * count / pc
+    # the same problems give the same eigenvalues and (up to rounding) eigenvectors
+    for b in range(0, pc, max(1, pc // 64)):
+        n = int(ns[b])
+        W, Z = binding.tridiag_eigvecs(d_all[off[b]:off[b + 1]], e_all[eoff[b]:eoff[b] + n - 1])
+        Wb = W_all[woff[b]:woff[b] + n]
+        assert torch.equal(W, Wb), f"problem {b}: eigenvalues differ"
+        Zb = Z_all[zoff[b]:zoff[b] + n * n].view(n, n)
+        worst = max(worst, float((Z - Zb).abs().max()))
+    out = {
+        "metric": "batched solves/s FP64 (plain one-problem-per-call path on the same GPU beside it)",
+        "value": count / t_batched,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1000.0 * t_batched,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{count} problems, n log-uniform [64, 2048] (seed 1), 25% glued "
+                               "Wilkinson, all eigenpairs", "sum_n": int(ns.sum())},
+        "plain": {"solves_per_s": count / t_plain, "s_total": t_plain,
+                  "calls_timed": pc, "extrapolated": pc < count},
+        "speedup_vs_plain": t_plain / t_batched,
+        "batched_vs_plain_max_dev": worst,
+        "phases_ms": {k: v[0] for k, v in phases.items()},
+        "phase_launches": {k: v[1] for k, v in phases.items()},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,9 +192,15 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (profiler counter calibration)")
+    ap.add_argument("--workload", choices=["laplacian", "batched", "serving"], default="laplacian")
+    ap.add_argument("--count", type=int, default=4096, help="batched: number of problems")
+    ap.add_argument("--plain-count", type=int, default=4096,
+                    help="batched: plain calls actually timed (rest extrapolated)")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
+    if args.gpus == 1 and args.workload == "batched":
+        return batched_bench(args.count, args.plain_count)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the per-GPU "
               "path and its multi-GPU sharding plan are described in DESIGN.md", file=sys.stderr)

@@ -71,6 +71,8 @@ typedef struct te_opts {
     double cluster_rtol;/* cluster gap as a multiple of ||T||_1 (default 1e-3)      */
     int coop_wgs;       /* cap on cooperative workgroups (0: fill the device)       */
     int _reserved1;
+    uint64_t ws_budget; /* device workspace budget in bytes for batched calls
+                           (0: half the free device memory, at most 64 GiB)         */
 } te_opts;
 
 /* Eigenpairs il..iu of T (bisection for W, then inverse iteration).
@@ -104,14 +106,18 @@ int tridiag_eigvecs_ex(const double *d, const double *e, int n, int il, int iu,
                        const te_opts *opt, void *ws, size_t ws_bytes, int *info,
                        hipStream_t stream);
 
-/* B independent problems in one pass.  Problem b has order
+/* B independent problems, processed together.  Problem b has order
  * n_b = off[b+1] - off[b]; its d entries are d_all[off[b] .. off[b+1]-1] and
  * its e entries e_all[off[b] - b .. off[b+1] - b - 2] (n_b - 1 of them).
  * il[b], iu[b] (host arrays) select its eigenvalues; W_all[woff[b] ..] receives
  * them and Z_all + zoff[b] its eigenvectors with leading dimension n_b, where
  * woff/zoff (host arrays of B entries) are caller-chosen offsets.  off, il, iu,
  * woff, zoff are HOST arrays; d_all, e_all, W_all, Z_all are device arrays.
- * All problems share one workspace allocation and one launch per phase.
+ * Consecutive problems are grouped into sub-batches whose workspace fits
+ * opt->ws_budget; each sub-batch runs every phase as one launch over all of
+ * its problems (their cluster chains run concurrently).  Synchronizes
+ * `stream` before returning.  Returns TE_ERR_WORKSPACE if a single problem
+ * does not fit the budget.
  * Argument positions: d_all=1 e_all=2 off=3 il=4 iu=5 W_all=6 woff=7 Z_all=8
  * zoff=9 B=10 opt=11. */
 int tridiag_eigvecs_batched(const double *d_all, const double *e_all, const int64_t *off,

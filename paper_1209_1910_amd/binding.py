@@ -33,7 +33,8 @@ class TeError(RuntimeError):
 class te_opts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("_reserved0", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("cluster_rtol", ctypes.c_double),
-                ("coop_wgs", ctypes.c_int), ("_reserved1", ctypes.c_int)]
+                ("coop_wgs", ctypes.c_int), ("_reserved1", ctypes.c_int),
+                ("ws_budget", ctypes.c_uint64)]
 
 
 _lib = None
@@ -99,12 +100,13 @@ def _check(fn, rc):
         raise TeError(fn, rc, lib().te_last_hip_error())
 
 
-def _opts(iters=None, seed=None, cluster_rtol=None, coop_wgs=None):
+def _opts(iters=None, seed=None, cluster_rtol=None, coop_wgs=None, ws_budget=None):
     o = te_opts()
     o.iters = int(iters or 0)
     o.seed = int(seed or 0)
     o.cluster_rtol = float(cluster_rtol or 0.0)
     o.coop_wgs = int(coop_wgs or 0)
+    o.ws_budget = int(ws_budget or 0)
     return o
 
 
@@ -224,6 +226,27 @@ def tridiag_eigvecs_ex(d, e, il=1, iu=None, W_given=None, ws=None, info=None, st
                                   _stream_ptr(stream))
     _check("tridiag_eigvecs_ex", rc)
     return W[:m], Z[:m], info
+
+
+def tridiag_eigvecs_batched_raw(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff, stream=None,
+                                **opts):
+    """Batched call on device tensors already laid out as the C-ABI expects;
+    off/il/iu/woff/zoff are host numpy arrays (int64, int32, int32, int64, int64)."""
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    il = np.ascontiguousarray(il, dtype=np.int32)
+    iu = np.ascontiguousarray(iu, dtype=np.int32)
+    woff = np.ascontiguousarray(woff, dtype=np.int64)
+    zoff = np.ascontiguousarray(zoff, dtype=np.int64)
+    o = _opts(**opts)
+    rc = lib().tridiag_eigvecs_batched(_vp(d_all.data_ptr()), _vp(e_all.data_ptr()),
+                                       off.ctypes.data_as(i64p), il.ctypes.data_as(ip),
+                                       iu.ctypes.data_as(ip), _vp(W_all.data_ptr()),
+                                       woff.ctypes.data_as(i64p), _vp(Z_all.data_ptr()),
+                                       zoff.ctypes.data_as(i64p), len(il), ctypes.byref(o),
+                                       _stream_ptr(stream))
+    _check("tridiag_eigvecs_batched", rc)
 
 
 def tridiag_eigvecs_batched(problems, stream=None, device="cuda", **opts):

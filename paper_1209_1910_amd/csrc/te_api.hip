@@ -92,15 +92,17 @@ struct Resolved {
   uint64_t seed;
   double rtol;
   int coop_wgs;
+  uint64_t ws_budget;
 };
 
 Resolved resolve(const te_opts *o) {
-  Resolved r{TE_DEFAULT_ITERS, TE_DEFAULT_SEED, 1e-3, 0};
+  Resolved r{TE_DEFAULT_ITERS, TE_DEFAULT_SEED, 1e-3, 0, 0};
   if (o) {
     if (o->iters > 0) r.iters = o->iters;
     if (o->seed) r.seed = o->seed;
     if (o->cluster_rtol > 0.0) r.rtol = o->cluster_rtol;
     if (o->coop_wgs > 0) r.coop_wgs = o->coop_wgs;
+    r.ws_budget = o->ws_budget;
   }
   return r;
 }
@@ -490,6 +492,46 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   return abort_flag ? TE_ERR_KERNEL : 0;
 }
 
+// Workspace bytes solve_problems needs for a set of problems (upper bound).
+size_t problems_bytes(const std::vector<ProblemDesc> &pd, size_t b0, size_t b1,
+                      const DeviceLimits &lim) {
+  size_t bytes = fixed_bytes((int)(b1 - b0));
+  int nmax = 0, mmax = 0, msum = 0;
+  for (size_t b = b0; b < b1; b++) {
+    const int m = pd[b].iu - pd[b].il + 1;
+    bytes += prob_layout(pd[b].n, m).total();
+    nmax = std::max(nmax, pd[b].n);
+    mmax = std::max(mmax, m);
+    msum += m;
+  }
+  return bytes + chain_bytes(nmax, mmax, std::max(lim.small, lim.coop), lim.coop, msum);
+}
+
+uint64_t default_budget() {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return (uint64_t)8 << 30;
+  const uint64_t cap = (uint64_t)64 << 30;
+  return std::min<uint64_t>(cap, fr / 2);
+}
+
+// Consecutive problems grouped greedily into sub-batches that fit the budget.
+int solve_batched(const std::vector<ProblemDesc> &pd, const Resolved &opt, hipStream_t stream) {
+  DeviceLimits lim = limits();
+  if (lim.device < 0 || lim.coop <= 0 || lim.small <= 0) return TE_ERR_NO_DEVICE;
+  const uint64_t budget = opt.ws_budget ? opt.ws_budget : default_budget();
+  size_t b0 = 0;
+  while (b0 < pd.size()) {
+    size_t b1 = b0 + 1;
+    if (problems_bytes(pd, b0, b1, lim) > budget) return TE_ERR_WORKSPACE;
+    while (b1 < pd.size() && problems_bytes(pd, b0, b1 + 1, lim) <= budget) b1++;
+    std::vector<ProblemDesc> sub(pd.begin() + b0, pd.begin() + b1);
+    const int rc = solve_problems(sub, nullptr, opt, nullptr, 0, nullptr, stream);
+    if (rc) return rc;
+    b0 = b1;
+  }
+  return 0;
+}
+
 }  // namespace
 }  // namespace te
 
@@ -681,7 +723,7 @@ int tridiag_eigvecs_batched(const double *d_all, const double *e_all, const int6
     pd[b].ldz = (int)nb;
   }
   if (any_e && !e_all) return -2;
-  return solve_problems(pd, nullptr, resolve(opt), nullptr, 0, nullptr, stream);
+  return solve_batched(pd, resolve(opt), stream);
 }
 
 }  // extern "C"
