@@ -181,6 +181,132 @@ def batched_bench(count: int, plain_count: int) -> int:
     return 0
 
 
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x, dtype=np.float64), q)) if len(x) else None
+
+
+def serving_bench(count: int, qps: float, budget_gib: float, lanes: int) -> int:
+    """Serving workload: a Poisson request trace (seed 2) replayed in real
+    time into the serving engine, then all at once (saturation), against the
+    plain one-problem-per-call path serving the same trace in FIFO order.
+    Latency is submission to results in host memory; the plain FIFO latencies
+    follow from its measured service times (a single FIFO server starts each
+    request when it has arrived and the previous one is done)."""
+    import numpy as np
+    import torch
+
+    from paper_1209_1910_amd import binding, inputs
+
+    reqs = inputs.serving_trace(count=count, qps=qps, seed=2)
+    ns = np.array([len(r.d) for r in reqs])
+    ms = np.array([r.iu - r.il + 1 for r in reqs])
+    arr = np.array([r.arrival_s for r in reqs])
+    budget = int(budget_gib * (1 << 30))
+    classes = [("n<1024", 0, 1024), ("1024<=n<4096", 1024, 4096), ("n>=4096", 4096, 1 << 30)]
+    say = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)  # noqa: E731
+    say(f"serving: {count} requests over {arr[-1]:.1f} s, sum n*m = {int((ns * ms).sum())}")
+
+    # warm-up: module load, device pools
+    d0, e0 = inputs.uniform_tridiag(512, 5)
+    with binding.Server(hbm_budget=budget, lanes=lanes) as s:
+        s.wait(s.submit(d0, e0))
+    W, Z = binding.tridiag_eigvecs(d0, e0)
+    torch.cuda.synchronize()
+
+    def served(real_time: bool):
+        with binding.Server(hbm_budget=budget, lanes=lanes) as s:
+            t0 = time.perf_counter()
+            ids = []
+            for k, r in enumerate(reqs):
+                if real_time:
+                    dt = t0 + r.arrival_s - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                ids.append(s.submit(r.d, r.e, r.il, r.iu))
+                if k % 10 == 9:
+                    say(f"submitted {k + 1}/{count}")
+            outs = []
+            for k, rid in enumerate(ids):
+                outs.append(s.wait(rid))
+                if k % 10 == 9:
+                    say(f"completed {k + 1}/{count}")
+            t = np.array([s.times(rid) for rid in ids])
+        lat = t[:, 2] - t[:, 0]
+        span = float(t[:, 2].max() - t[:, 0].min())
+        return outs, lat, span
+
+    say("served, real-time arrivals")
+    out_q, lat_q, span_q = served(True)
+    say("served, all requests at t=0")
+    out_s, lat_s, span_s = served(False)
+    del out_s
+
+    say("plain path, one call per request")
+    svc = np.zeros(count)
+    worst = 0.0
+    identical = True
+    dev = torch.device("cuda:0")
+    for k, r in enumerate(reqs):
+        t0 = time.perf_counter()
+        d = torch.from_numpy(r.d).to(dev)
+        e = torch.from_numpy(r.e).to(dev)
+        W, Z = binding.tridiag_eigvecs(d, e, r.il, r.iu)
+        Wh, Zh = W.cpu().numpy(), Z.cpu().numpy()
+        svc[k] = time.perf_counter() - t0
+        Ws, Zs = out_q[k]
+        identical &= bool(np.array_equal(Wh, Ws) and np.array_equal(Zh, Zs))
+        worst = max(worst, float(np.abs(Zh - Zs).max()) if Zh.size else 0.0)
+        out_q[k] = None
+        if k % 10 == 9:
+            say(f"plain {k + 1}/{count}")
+    done = np.zeros(count)
+    prev = 0.0
+    for k in range(count):
+        prev = max(arr[k], prev) + svc[k]
+        done[k] = prev
+    lat_p = done - arr
+    span_p = float(done[-1] - arr[0])
+
+    def summ(lat, span):
+        return {"p50_s": _pct(lat, 50), "p99_s": _pct(lat, 99), "mean_s": float(np.mean(lat)),
+                "solves_per_s": count / span, "makespan_s": span}
+
+    by_class = {}
+    for name, lo, hi in classes:
+        sel = (ns >= lo) & (ns < hi)
+        by_class[name] = {
+            "count": int(sel.sum()),
+            "served_p50_s": _pct(lat_q[sel], 50), "served_p99_s": _pct(lat_q[sel], 99),
+            "plain_fifo_p50_s": _pct(lat_p[sel], 50), "plain_fifo_p99_s": _pct(lat_p[sel], 99),
+            "plain_service_s": float(svc[sel].sum()),
+        }
+    sat_plain = count / float(svc.sum())
+    out = {
+        "metric": "served solves/s FP64, serving trace with all requests queued "
+                  "(plain one-problem-per-call path on the same GPU beside it)",
+        "value": count / span_s,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1000.0 * span_s,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving trace: {count} requests, Poisson {qps} QPS (seed 2), "
+                               "n log-uniform [256, 16384], 70% U(-1,1) / 30% glued Wilkinson, "
+                               "50% all eigenpairs else a random 10% index range",
+                   "hbm_budget_gib": budget_gib, "lanes": lanes},
+        "saturation": {"served_solves_per_s": count / span_s, "plain_solves_per_s": sat_plain,
+                       "speedup_vs_plain": (count / span_s) / sat_plain,
+                       "served_p50_s": _pct(lat_s, 50), "served_p99_s": _pct(lat_s, 99)},
+        "at_qps": {"qps": qps, "served": summ(lat_q, span_q), "plain_fifo": summ(lat_p, span_p)},
+        "by_size_class": by_class,
+        "served_vs_plain_identical": identical,
+        "served_vs_plain_max_dev": worst,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,15 +322,21 @@ def main() -> int:
     ap.add_argument("--count", type=int, default=4096, help="batched: number of problems")
     ap.add_argument("--plain-count", type=int, default=4096,
                     help="batched: plain calls actually timed (rest extrapolated)")
+    ap.add_argument("--requests", type=int, default=60, help="serving: trace length")
+    ap.add_argument("--qps", type=float, default=1.0, help="serving: arrival rate")
+    ap.add_argument("--budget-gib", type=float, default=32.0, help="serving: HBM budget")
+    ap.add_argument("--lanes", type=int, default=3, help="serving: concurrent rounds")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the library runs "
+              "each problem on a single device", file=sys.stderr)
+        return 2
     if args.copy_calibration:
         return copy_calibration()
-    if args.gpus == 1 and args.workload == "batched":
+    if args.workload == "batched":
         return batched_bench(args.count, args.plain_count)
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the per-GPU "
-              "path and its multi-GPU sharding plan are described in DESIGN.md", file=sys.stderr)
-        return 2
+    if args.workload == "serving":
+        return serving_bench(args.requests, args.qps, args.budget_gib, args.lanes)
 
     import numpy as np
     import torch

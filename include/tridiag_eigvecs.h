@@ -142,6 +142,61 @@ int tridiag_eigvals(const double *d, const double *e, int n, int il, int iu, dou
 int tridiag_clusters(const double *W, int m, double tol, int *start, int *size, int *ncl,
                      hipStream_t stream);
 
+/* ---- Serving engine ----
+ * A request loop for eigenvector solves of different sizes arriving over
+ * time (continuous batching; the method and its results are those of
+ * tridiag_eigvecs, problem by problem, bit for bit).  Requests wait in two
+ * FIFO queues, light and heavy, by the size of their per-eigenvalue state
+ * (n * m below or at least 2^22 entries).  Each of `lanes` host threads owns a
+ * stream; a free lane takes the class of the oldest waiting request and
+ * admits from that queue, in order, every request whose device memory (its
+ * inputs, outputs and workspace) still fits the HBM budget beside the rounds
+ * in flight, up to 512.  The round then runs every phase as one launch over
+ * its requests, copies W and Z to the caller's buffers and frees its memory;
+ * rounds on different lanes overlap on the device.  A request whose own need
+ * exceeds the budget completes at once with TE_ERR_WORKSPACE.
+ * Memory from the round's device allocations stays cached in the device's
+ * stream-ordered pool after use, so the process's device footprint can exceed
+ * the budget by the pool's fragmentation.
+ * All functions are thread-safe. */
+typedef struct te_server te_server;
+
+/* Start a server on the current device.  hbm_budget: device bytes that
+ * admitted requests may hold at once (0: half the free device memory, at most
+ * 64 GiB).  lanes: concurrent rounds (0: 3; at most 64).  opt: as for
+ * tridiag_eigvecs_ex (may be NULL); coop_wgs = 0 caps the cooperative chain
+ * kernel at three quarters of the device's compute units, so that the other
+ * lanes keep running beside it.  Returns NULL if there is no usable device or
+ * an argument is invalid. */
+te_server *te_server_create(uint64_t hbm_budget, int lanes, const te_opts *opt);
+
+/* Queue one request: eigenpairs il..iu of T = tridiag(e, d, e) of order n.
+ * d (n) and e (n - 1) are HOST arrays, copied before the call returns.  W (m
+ * doubles) and Z (column-major, leading dimension ldz >= n, m columns) are
+ * host or device memory that receive the results when the request completes;
+ * they must stay valid until then.  *id receives the request id.
+ * Argument positions: server=1 d=2 e=3 n=4 il=5 iu=6 W=7 Z=8 ldz=9 id=10;
+ * TE_ERR_NO_DEVICE if the server is shutting down. */
+int te_server_submit(te_server *server, const double *d, const double *e, int n, int il, int iu,
+                     double *W, double *Z, int ldz, int64_t *id);
+
+/* 1 if request id has completed (then *rc, if rc is non-NULL, is its result
+ * code, 0 or a TE_ERR_* value), 0 if it is still queued or running, -1 for a
+ * NULL server, -2 for an unknown id. */
+int te_server_poll(te_server *server, int64_t id, int *rc);
+
+/* Block until request id has completed; returns as te_server_poll. */
+int te_server_wait(te_server *server, int64_t id, int *rc);
+
+/* Seconds since te_server_create at which request id was submitted, admitted
+ * into a round and completed (results in the caller's buffers).  Any pointer
+ * may be NULL.  Returns as te_server_poll. */
+int te_server_times(te_server *server, int64_t id, double *t_submit, double *t_start,
+                    double *t_done);
+
+/* Finish every queued request, stop the lanes and free the server. */
+void te_server_destroy(te_server *server);
+
 /* Device-time accounting of the library's kernels, for benchmarks and
  * profiling.  When enabled, every entry point records hipEvents around each
  * kernel it launches, on the stream it launches it on, and adds the elapsed

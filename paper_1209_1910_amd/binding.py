@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libtridiag_eigvecs.so")
 TE_DEFAULT_SEED = 0x12091910
 SYMBOLS = ("tridiag_eigvecs", "tridiag_eigvecs_given_w", "tridiag_eigvecs_workspace_bytes",
            "tridiag_eigvecs_ex", "tridiag_eigvecs_batched", "tridiag_eigvals", "tridiag_clusters",
+           "te_server_create", "te_server_submit", "te_server_poll", "te_server_wait",
+           "te_server_times", "te_server_destroy",
            "te_timing_enable", "te_timing_reset", "te_timing_read", "te_last_hip_error")
 PHASES = ("setup", "bisect", "clusters", "first_solves", "transpose", "chain_small",
           "chain_coop", "finalize")
@@ -59,6 +61,15 @@ def lib():
                                               ctypes.POINTER(te_opts), _vp]
         L.tridiag_eigvals.argtypes = [_vp, _vp, i, i, i, _vp, _vp]
         L.tridiag_clusters.argtypes = [_vp, i, ctypes.c_double, _vp, _vp, _vp, _vp]
+        L.te_server_create.argtypes = [ctypes.c_uint64, i, ctypes.POINTER(te_opts)]
+        L.te_server_create.restype = _vp
+        L.te_server_submit.argtypes = [_vp, _vp, _vp, i, i, i, _vp, _vp, i, i64p]
+        L.te_server_poll.argtypes = [_vp, ctypes.c_int64, ip]
+        L.te_server_wait.argtypes = [_vp, ctypes.c_int64, ip]
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.te_server_times.argtypes = [_vp, ctypes.c_int64, dp, dp, dp]
+        L.te_server_destroy.argtypes = [_vp]
+        L.te_server_destroy.restype = None
         L.te_timing_enable.argtypes = [i]
         L.te_timing_enable.restype = None
         L.te_timing_reset.restype = None
@@ -297,3 +308,89 @@ def tridiag_eigvecs_batched(problems, stream=None, device="cuda", **opts):
         Z = Z_all[zoff[b]: zoff[b] + m * n].view(m, n)
         out.append((W, Z))
     return out
+
+
+class Server:
+    """Serving engine (te_server_*): submit host problems, collect host results.
+
+    ``submit`` copies d and e and allocates the host outputs W (m,) and Z (m, n)
+    (row j of Z is the eigenvector of W[j]); they are filled when the request
+    completes.  Use as a context manager, or call ``close``.
+    """
+
+    def __init__(self, hbm_budget=0, lanes=0, iters=None, seed=None, cluster_rtol=None,
+                 coop_wgs=None):
+        self._o = _opts(iters, seed, cluster_rtol, coop_wgs)
+        h = lib().te_server_create(int(hbm_budget), int(lanes), ctypes.byref(self._o))
+        if not h:
+            raise TeError("te_server_create", -1)
+        self._h = ctypes.c_void_p(h)
+        self._out = {}
+
+    def submit(self, d, e, il=1, iu=None):
+        d = np.ascontiguousarray(_host_f64(d))
+        e = np.ascontiguousarray(_host_f64(e))
+        n = int(d.shape[0])
+        iu = n if iu is None else int(iu)
+        m = iu - int(il) + 1
+        W = np.empty(max(m, 0), dtype=np.float64)
+        Z = np.empty((max(m, 0), n), dtype=np.float64)
+        rid = ctypes.c_int64(0)
+        rc = lib().te_server_submit(self._h, d.ctypes.data, e.ctypes.data if e.size else None, n,
+                                    int(il), iu, W.ctypes.data, Z.ctypes.data, n,
+                                    ctypes.byref(rid))
+        _check("te_server_submit", rc)
+        self._out[rid.value] = (W, Z)
+        return rid.value
+
+    def poll(self, rid):
+        """True once request rid has completed (raises if it failed)."""
+        rc = ctypes.c_int(0)
+        r = lib().te_server_poll(self._h, int(rid), ctypes.byref(rc))
+        if r < 0:
+            raise TeError("te_server_poll", r)
+        if r == 1:
+            _check("te_server request", rc.value)
+        return r == 1
+
+    def wait(self, rid):
+        """Block until request rid completes; returns (W, Z) (host arrays)."""
+        rc = ctypes.c_int(0)
+        r = lib().te_server_wait(self._h, int(rid), ctypes.byref(rc))
+        if r < 0:
+            raise TeError("te_server_wait", r)
+        _check("te_server request", rc.value)
+        return self._out[int(rid)]
+
+    def result_code(self, rid):
+        rc = ctypes.c_int(0)
+        r = lib().te_server_wait(self._h, int(rid), ctypes.byref(rc))
+        if r < 0:
+            raise TeError("te_server_wait", r)
+        return rc.value
+
+    def times(self, rid):
+        """(t_submit, t_start, t_done) in seconds since the server started."""
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        r = lib().te_server_times(self._h, int(rid), ctypes.byref(a), ctypes.byref(b),
+                                  ctypes.byref(c))
+        if r < 0:
+            raise TeError("te_server_times", r)
+        return a.value, b.value, c.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().te_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,8 +9,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtridiag_eigvecs.so")
-SOURCES = [os.path.join(CSRC, "te_kernels.hip"), os.path.join(CSRC, "te_api.hip")]
-HEADERS = [os.path.join(CSRC, "te_internal.h"), os.path.join(ROOT, "include", "tridiag_eigvecs.h")]
+SOURCES = [os.path.join(CSRC, "te_kernels.hip"), os.path.join(CSRC, "te_api.hip"),
+           os.path.join(CSRC, "te_server.hip")]
+HEADERS = [os.path.join(CSRC, "te_internal.h"), os.path.join(CSRC, "te_host.h"),
+           os.path.join(ROOT, "include", "tridiag_eigvecs.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("TE_OFFLOAD_ARCH", "gfx950")

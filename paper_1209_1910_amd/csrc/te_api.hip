@@ -3,23 +3,25 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <mutex>
 #include <numeric>
+#include <thread>
 #include <vector>
 
-#include "../../include/tridiag_eigvecs.h"
-#include "te_internal.h"
+#include "te_host.h"
 
 namespace te {
-namespace {
 
 thread_local int g_last_hip = 0;
 
-inline int hip_fail(hipError_t e) {
+int hip_fail(hipError_t e) {
   g_last_hip = (int)e;
   return TE_ERR_HIP;
 }
+
+namespace {
 
 #define TE_CHECK(call)                          \
   do {                                          \
@@ -87,57 +89,6 @@ inline size_t even(size_t x) { return (x + 1) & ~(size_t)1; }
 // exceeds this many entries; smaller chains run one per workgroup.
 constexpr size_t kLargeEntries = (size_t)1 << 20;
 
-struct Resolved {
-  int iters;
-  uint64_t seed;
-  double rtol;
-  int coop_wgs;
-  uint64_t ws_budget;
-};
-
-Resolved resolve(const te_opts *o) {
-  Resolved r{TE_DEFAULT_ITERS, TE_DEFAULT_SEED, 1e-3, 0, 0};
-  if (o) {
-    if (o->iters > 0) r.iters = o->iters;
-    if (o->seed) r.seed = o->seed;
-    if (o->cluster_rtol > 0.0) r.rtol = o->cluster_rtol;
-    if (o->coop_wgs > 0) r.coop_wgs = o->coop_wgs;
-    r.ws_budget = o->ws_budget;
-  }
-  return r;
-}
-
-struct DeviceLimits {
-  int device = -1;
-  int coop = 0;   // co-resident chain workgroups (cooperative kernel)
-  int small = 0;  // resident workgroups of the small-chain kernel
-};
-
-DeviceLimits limits() {
-  static std::mutex mu;
-  static DeviceLimits cache[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return DeviceLimits{};
-  std::lock_guard<std::mutex> lk(mu);
-  if (dev < 0 || dev >= 64) return DeviceLimits{};
-  if (cache[dev].device != dev) {
-    // Keep freed stream-ordered allocations in the device's default pool, so
-    // repeated calls do not map and unmap their (possibly tens of GB of)
-    // workspace every time.
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-      uint64_t thr = UINT64_MAX;
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    DeviceLimits L;
-    L.device = dev;
-    L.coop = coop_max_wgs(dev);
-    L.small = small_max_wgs(dev);
-    cache[dev] = L;
-  }
-  return cache[dev];
-}
-
 // Per-problem sizes of the workspace pieces (bytes, each aligned).
 struct ProbLayout {
   size_t e2, nrm, pos, cls, clz, ncl, V, Ll, U1, U2, U3, Sw, Lrec, Lswb, Y, Yr, T, Tr, prm, info;
@@ -186,12 +137,6 @@ struct Carve {
   }
 };
 
-struct ProblemDesc {
-  const double *d, *e;
-  int n, il, iu;
-  double *W, *Z;
-  int ldz;
-};
 
 // Everything one call needs after the problems are described.
 struct Run {
@@ -279,6 +224,161 @@ void plan_groups(const std::vector<ChainItem> &items, const std::vector<double> 
   }
 }
 
+}  // namespace
+
+Resolved resolve(const te_opts *o) {
+  Resolved r{TE_DEFAULT_ITERS, TE_DEFAULT_SEED, 1e-3, 0, 0};
+  if (o) {
+    if (o->iters > 0) r.iters = o->iters;
+    if (o->seed) r.seed = o->seed;
+    if (o->cluster_rtol > 0.0) r.rtol = o->cluster_rtol;
+    if (o->coop_wgs > 0) r.coop_wgs = o->coop_wgs;
+    r.ws_budget = o->ws_budget;
+  }
+  return r;
+}
+
+DeviceLimits limits() {
+  static std::mutex mu;
+  static DeviceLimits cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DeviceLimits{};
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev < 0 || dev >= 64) return DeviceLimits{};
+  if (cache[dev].device != dev) {
+    // Keep freed stream-ordered allocations in the device's default pool, so
+    // repeated calls do not map and unmap their (possibly tens of GB of)
+    // workspace every time.
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    DeviceLimits L;
+    L.device = dev;
+    L.coop = coop_max_wgs(dev);
+    L.small = small_max_wgs(dev);
+    cache[dev] = L;
+  }
+  return cache[dev];
+}
+
+void DeviceGate::lock_shared() {
+  std::unique_lock<std::mutex> lk(mu);
+  cv.wait(lk, [&] { return !writer && writers_waiting == 0; });
+  readers++;
+}
+
+void DeviceGate::unlock_shared() {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    readers--;
+  }
+  cv.notify_all();
+}
+
+void DeviceGate::lock_exclusive() {
+  std::unique_lock<std::mutex> lk(mu);
+  writers_waiting++;
+  cv.wait(lk, [&] { return !writer && readers == 0; });
+  writers_waiting--;
+  writer = true;
+}
+
+void DeviceGate::unlock_exclusive() {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    writer = false;
+  }
+  cv.notify_all();
+}
+
+DeviceGate &device_gate(int device) {
+  static DeviceGate gates[64];
+  return gates[device & 63];
+}
+
+SharedHold::SharedHold() {
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) g_ = &device_gate(dev);
+  acquire();
+}
+
+void SharedHold::acquire() {
+  if (g_ && !held_) {
+    g_->lock_shared();
+    held_ = true;
+  }
+}
+
+void SharedHold::release() {
+  if (g_ && held_) {
+    g_->unlock_shared();
+    held_ = false;
+  }
+}
+
+namespace {
+
+// Launch the cooperative chain kernel under the device gate (see DeviceGate)
+// and wait for it to complete.  The caller holds no shared hold and has
+// synchronized its stream.
+int run_coop(const DeviceLimits &lim, const Prob *probs, const ChainItem *items,
+             const Group *groups, const int *wg_group, unsigned *bars, int *abort_flag,
+             ChainScratch scr, int nwg, int iters, PhaseTimer &tm, hipStream_t stream) {
+  DeviceGate &g = device_gate(lim.device);
+  std::lock_guard<std::mutex> one(g.coop);
+  if (!g.started_host) {
+    int *h = nullptr;
+    if (hipHostMalloc((void **)&h, sizeof(int) * (size_t)lim.coop, hipHostMallocCoherent) ==
+        hipSuccess) {
+      int *dp = nullptr;
+      if (hipHostGetDevicePointer((void **)&dp, h, 0) == hipSuccess) {
+        g.started_host = h;
+        g.started_dev = dp;
+        g.started_cap = lim.coop;
+      } else {
+        (void)hipHostFree(h);
+      }
+    }
+    (void)hipGetLastError();
+  }
+  int *started = (g.started_dev && nwg <= g.started_cap) ? g.started_dev : nullptr;
+  if (started) {
+    for (int w = 0; w < nwg; w++) __atomic_store_n(&g.started_host[w], 0, __ATOMIC_RELAXED);
+    __atomic_thread_fence(__ATOMIC_SEQ_CST);
+  }
+  g.lock_exclusive();
+  tm.begin(PH_COOP);
+  hipError_t e = launch_chain_coop(probs, items, groups, wg_group, bars, abort_flag, started, scr,
+                                   nwg, iters, stream);
+  tm.end();
+  if (e != hipSuccess) {
+    g.unlock_exclusive();
+    return hip_fail(e);
+  }
+  // Hold the device until every workgroup is resident (or the grid is done).
+  for (;;) {
+    if (started) {
+      int cnt = 0;
+      for (int w = 0; w < nwg; w++) cnt += __atomic_load_n(&g.started_host[w], __ATOMIC_ACQUIRE);
+      if (cnt == nwg) break;
+    }
+    const hipError_t q = hipStreamQuery(stream);
+    if (q == hipSuccess) break;
+    if (q != hipErrorNotReady) {
+      g.unlock_exclusive();
+      return hip_fail(q);
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(started ? 10 : 200));
+  }
+  g.unlock_exclusive();
+  TE_CHECK(hipStreamSynchronize(stream));  // one cooperative grid in flight at a time
+  return 0;
+}
+
+}  // namespace
+
 // The whole method for a set of problems.  ws may be null (library-owned
 // workspace via hipMallocAsync).  W_given: device array of mtotal eigenvalues
 // or null.
@@ -287,6 +387,7 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   const int nprob = (int)pd.size();
   DeviceLimits lim = limits();
   if (lim.device < 0 || lim.coop <= 0 || lim.small <= 0) return TE_ERR_NO_DEVICE;
+  SharedHold hold;
 
   Run R;
   R.hp.resize(nprob);
@@ -472,10 +573,12 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
     TE_CHECK(hipMemcpyAsync(dwg, wg_group.data(), sizeof(int) * coop_nwg, hipMemcpyHostToDevice,
                             stream));
     TE_CHECK(launch_fill_i32((int *)dbars, kBarWords * (size_t)coop_nwg, 0, stream));
-    tm.begin(PH_COOP);
-    TE_CHECK(launch_chain_coop(R.dprobs, ditems, dgroups, dwg, dbars, dflags, scr, coop_nwg,
-                               opt.iters, stream));
-    tm.end();
+    TE_CHECK(hipStreamSynchronize(stream));
+    hold.release();
+    const int rc = run_coop(lim, R.dprobs, ditems, dgroups, dwg, dbars, dflags, scr, coop_nwg,
+                            opt.iters, tm, stream);
+    hold.acquire();
+    if (rc) return rc;
   }
   tm.begin(PH_FINAL);
   TE_CHECK(launch_finalize(R.dprobs, nprob, R.dloff, R.mtotal, stream));
@@ -532,7 +635,6 @@ int solve_batched(const std::vector<ProblemDesc> &pd, const Resolved &opt, hipSt
   return 0;
 }
 
-}  // namespace
 }  // namespace te
 
 using namespace te;
@@ -634,6 +736,7 @@ int tridiag_eigvals(const double *d, const double *e, int n, int il, int iu, dou
   if (iu < il || iu > n) return -5;
   if (!W) return -6;
   if (limits().device < 0) return TE_ERR_NO_DEVICE;
+  SharedHold hold;
   const int m = iu - il + 1;
   const size_t bytes = fixed_bytes(1) + align_up(sizeof(double) * std::max(n - 1, 1)) +
                        align_up(sizeof(Params));
@@ -670,6 +773,7 @@ int tridiag_clusters(const double *W, int m, double tol, int *start, int *size, 
   if (!size) return -5;
   if (!ncl) return -6;
   if (limits().device < 0) return TE_ERR_NO_DEVICE;
+  SharedHold hold;
   const size_t bytes = fixed_bytes(1) + align_up(sizeof(Params)) + align_up(sizeof(int) * m);
   char *base = nullptr;
   TE_CHECK(hipMallocAsync((void **)&base, bytes, stream));

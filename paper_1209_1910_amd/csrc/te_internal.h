@@ -96,8 +96,10 @@ hipError_t launch_transpose(const Prob *probs, int nprob, int nmax, int mmax, hi
 hipError_t launch_chain_small(const Prob *probs, const ChainItem *items, int nitems,
                               int *counter, ChainScratch scr, int nwg, int iters,
                               hipStream_t s);
+// started: null, or one host-coherent int per workgroup that the workgroup
+// sets to 1 when it begins (the host waits on it for residency).
 hipError_t launch_chain_coop(const Prob *probs, const ChainItem *items, const Group *groups,
-                             const int *wg_group, unsigned *bars, int *abort_flag,
+                             const int *wg_group, unsigned *bars, int *abort_flag, int *started,
                              ChainScratch scr, int nwg, int iters, hipStream_t s);
 hipError_t launch_finalize(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
                            hipStream_t s);

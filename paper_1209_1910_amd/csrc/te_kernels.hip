@@ -505,19 +505,18 @@ struct Scr {
   double *x, *xp, *s, *r, *xpp;    // mmax + 2 each (offset by the start parity)
   double *carry;                   // n / 64 + 8: carries into the scan chunks
   double *csum;                    // 2 (n / 64) + 16: chunk summaries (A, B)
-  double *red;                     // nwg + 8
 };
 
 __host__ __device__ inline size_t even_up(size_t x) { return (x + 1) & ~(size_t)1; }
 
-__host__ __device__ inline size_t scr_doubles(int nmax, int mmax, int nwg) {
+__host__ __device__ inline size_t scr_doubles(int nmax, int mmax) {
   return even_up(5 * even_up((size_t)nmax) + 5 * even_up((size_t)mmax + 2) +
-                 even_up((size_t)nmax / 64 + 8) + even_up(2 * ((size_t)nmax / 64) + 16) +
-                 (size_t)nwg + 8 + 64);
+                 even_up((size_t)nmax / 64 + 8) + even_up(2 * ((size_t)nmax / 64) + 16) + 64);
 }
 
 size_t chain_scratch_doubles(int nmax, int mmax, int nwg_in_group) {
-  return scr_doubles(nmax, mmax, nwg_in_group);
+  (void)nwg_in_group;
+  return scr_doubles(nmax, mmax);
 }
 
 __device__ inline Scr make_scr(double *base, int nmax, int mmax, int parity) {
@@ -535,8 +534,7 @@ __device__ inline Scr make_scr(double *base, int nmax, int mmax, int parity) {
   S.r = p + parity; p += mm;
   S.xpp = p + parity; p += mm;
   S.carry = p; p += even_up((size_t)nmax / 64 + 8);
-  S.csum = p; p += even_up(2 * ((size_t)nmax / 64) + 16);
-  S.red = p;
+  S.csum = p;
   return S;
 }
 
@@ -624,31 +622,43 @@ __device__ __forceinline__ bool fold_valid(int gw, int nw, int t, int cnt) {
   return (t & 1) ? (cnt - 1 - p > p) : true;
 }
 
-// Sum over the group of per-lane partials `part`: WG partial to red[rank],
-// barrier, then every WG sums red[0..size) in the same fixed order.
+// Sum of squares of x[i0..n) for the whole group, in one fixed order that
+// depends on neither the number of workgroups nor their size: after the group
+// barrier (which also publishes x), each workgroup reads the whole range with
+// 256 virtual lanes (lane v takes i0 + v, i0 + v + 256, ... into eight
+// accumulators combined pairwise), reduces each 64-lane wave by the fixed
+// butterfly and adds the four wave totals pairwise.  So a cluster's chain
+// gives the same bits on one workgroup or many, alone or batched.
 // Returns false on abort.
+constexpr int kSumLanes = 256;
+
 template <int NT>
-__device__ bool grp_sum(Ctx &c, double part, double *red, double &out) {
-  constexpr int NW = NT / kWave;
-  __shared__ double s_w[NW];
-  __shared__ double s_tot;
-  part = wave_sum(part);
-  if (c.lane == 0) s_w[c.wave] = part;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int q = 0; q < NW; q++) t += s_w[q];
-    red[c.rank] = t;
-  }
+__device__ bool grp_sumsq(Ctx &c, const double *x, int i0, int n, double &out) {
+  static_assert(NT >= kSumLanes, "group sums need 256 threads");
+  constexpr int kStep = 8 * kSumLanes;
+  __shared__ double s_p[kSumLanes / kWave];
   if (!grp_sync<NT>(c)) return false;
-  if (c.wave == 0) {
-    double t = 0.0;
-    for (int r = c.lane; r < c.size; r += kWave) t += red[r];
-    t = wave_sum(t);
-    if (c.lane == 0) s_tot = t;
+  if (threadIdx.x < kSumLanes) {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int i = i0 + (int)threadIdx.x;
+    for (; i + 7 * kSumLanes < n; i += kStep) {
+      double t[8];
+#pragma unroll
+      for (int r = 0; r < 8; r++) t[r] = x[i + r * kSumLanes];
+#pragma unroll
+      for (int r = 0; r < 8; r++) a[r] = fma(t[r], t[r], a[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 7; r++) {
+      const int ir = i + r * kSumLanes;
+      if (ir < n) a[r] = fma(x[ir], x[ir], a[r]);
+    }
+    double p = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    p = wave_sum(p);
+    if (c.lane == 0) s_p[c.wave] = p;
   }
   __syncthreads();
-  out = s_tot;
+  out = (s_p[0] + s_p[1]) + (s_p[2] + s_p[3]);
   return true;
 }
 
@@ -839,13 +849,9 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
   {
     const double *z = cv.Z;
     const double *z1 = cv.Z + cv.ldz;
-    double part = 0.0;
-    for (int i = gtid; i < n; i += gthreads) {
-      part = fma(z[i], z[i], part);
-      S.v[i] = z1[i];
-    }
+    for (int i = gtid; i < n; i += gthreads) S.v[i] = z1[i];
     double nz2;
-    if (!grp_sum<NT>(cx, part, S.red, nz2)) return false;
+    if (!grp_sumsq<NT>(cx, z, 0, n, nz2)) return false;
     const double z0 = z[0];
     const double g = -(z0 >= 0.0 ? 1.0 : -1.0) * sqrt(nz2);
     for (int i = gtid; i < n; i += gthreads) {
@@ -878,17 +884,12 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
       }
       if (!grp_sync<NT>(cx)) return false;
       // P3: u = v_hat - Yhat_c x' over rows c..n-1, and ||u||^2
-      double part = 0.0;
       for (int i = c + cx.gw; i < n; i += cx.nw) {
         const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xp, 0, c, lane);
-        const double ui = vin[i] - acc;
-        if (lane == 0) {
-          S.u[i] = ui;
-          part = fma(ui, ui, part);
-        }
+        if (lane == 0) S.u[i] = vin[i] - acc;
       }
       double beta2;
-      if (!grp_sum<NT>(cx, part, S.red, beta2)) return false;
+      if (!grp_sumsq<NT>(cx, S.u, c, n, beta2)) return false;
       // P4: Householder vector and s = Yhat_c^T y_hat
       const double alpha = S.u[c];
       const double beta = sqrt(beta2);
@@ -937,16 +938,11 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
       // are shorter (min(i, c) + 1 entries): folded assignment.
       const bool last = (k == iters);
       double *qout = last ? (cv.Z + (size_t)c * cv.ldz) : S.q;
-      double qpart = 0.0;
       for (int t = 0; fold_valid(cx.gw, cx.nw, t, n); t++) {
         const int i = fold_index(cx.gw, cx.nw, t, n);
         const int l1 = (i < c ? i : c) + 1;
         const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xpp, 0, l1, lane);
-        const double qi = (i == c) ? acc - 1.0 : acc;
-        if (lane == 0) {
-          qout[i] = qi;
-          qpart = fma(qi, qi, qpart);
-        }
+        if (lane == 0) qout[i] = (i == c) ? acc - 1.0 : acc;
       }
       if (last) {
         if (c + 1 < cv.M) {
@@ -957,7 +953,7 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
       } else {
         // P7: next iterate v = (T - lambda I)^{-1} q / ||q||
         double qn2;
-        if (!grp_sum<NT>(cx, qpart, S.red, qn2)) return false;
+        if (!grp_sumsq<NT>(cx, S.q, 0, n, qn2)) return false;
         if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(qn2))) return false;
       }
     }
@@ -1009,7 +1005,11 @@ __global__ void __launch_bounds__(kCoopThreads) k_chain_coop(const Prob *__restr
                                                              const Group *__restrict__ groups,
                                                              const int *__restrict__ wg_group,
                                                              unsigned *bars, int *abort_flag,
-                                                             ChainScratch scr, int iters) {
+                                                             int *started, ChainScratch scr,
+                                                             int iters) {
+  // Residency report to the host (host-coherent memory; may be null).
+  if (started && threadIdx.x == 0)
+    __hip_atomic_store(started + blockIdx.x, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   const int g = wg_group[blockIdx.x];
   if (g < 0) return;
   const Group G = groups[g];
@@ -1049,16 +1049,17 @@ static bool coop_launch_enabled() {
 }
 
 hipError_t launch_chain_coop(const Prob *probs, const ChainItem *items, const Group *groups,
-                             const int *wg_group, unsigned *bars, int *abort_flag,
+                             const int *wg_group, unsigned *bars, int *abort_flag, int *started,
                              ChainScratch scr, int nwg, int iters, hipStream_t s) {
   if (nwg <= 0) return hipSuccess;
   if (!coop_launch_enabled()) {
     hipLaunchKernelGGL(k_chain_coop, dim3(nwg), dim3(kCoopThreads), 0, s, probs, items, groups,
-                       wg_group, bars, abort_flag, scr, iters);
+                       wg_group, bars, abort_flag, started, scr, iters);
     return hipGetLastError();
   }
-  void *args[] = {(void *)&probs, (void *)&items, (void *)&groups, (void *)&wg_group,
-                  (void *)&bars, (void *)&abort_flag, (void *)&scr, (void *)&iters};
+  void *args[] = {(void *)&probs,     (void *)&items,   (void *)&groups,
+                  (void *)&wg_group,  (void *)&bars,    (void *)&abort_flag,
+                  (void *)&started,   (void *)&scr,     (void *)&iters};
   return hipLaunchCooperativeKernel((const void *)k_chain_coop, dim3(nwg), dim3(kCoopThreads),
                                     args, 0, s);
 }

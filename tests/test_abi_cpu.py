@@ -18,7 +18,8 @@ HEADER = os.path.join(ROOT, "include", "tridiag_eigvecs.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:int|size_t|void)\s+\**\s*(\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:int|size_t|void|te_server)\s+\**\s*(\w+)\s*\(", src,
+                       flags=re.M)
     return sorted(set(names))
 
 
@@ -67,3 +68,29 @@ def test_other_entry_points_argument_errors():
     o.iters = 3
     assert L.tridiag_eigvecs_ex(P, P, 10, 1, 10, NULL, P, P, 10, ctypes.byref(o), NULL, 1 << 40,
                                 NULL, NULL) == -11
+
+
+def test_server_argument_errors():
+    L = binding.lib()
+    rid = ctypes.c_int64(0)
+    i64 = ctypes.byref(rid)
+    # server handle checked first; then the request arguments in order
+    assert L.te_server_submit(NULL, P, P, 10, 1, 10, P, P, 10, i64) == -1
+    assert L.te_server_submit(P, NULL, P, 10, 1, 10, P, P, 10, i64) == -2
+    assert L.te_server_submit(P, P, NULL, 10, 1, 10, P, P, 10, i64) == -3
+    assert L.te_server_submit(P, P, P, 0, 1, 1, P, P, 10, i64) == -4
+    assert L.te_server_submit(P, P, P, 10, 0, 10, P, P, 10, i64) == -5
+    assert L.te_server_submit(P, P, P, 10, 3, 2, P, P, 10, i64) == -6
+    assert L.te_server_submit(P, P, P, 10, 1, 10, NULL, P, 10, i64) == -7
+    assert L.te_server_submit(P, P, P, 10, 1, 10, P, NULL, 10, i64) == -8
+    assert L.te_server_submit(P, P, P, 10, 1, 10, P, P, 9, i64) == -9
+    assert L.te_server_submit(P, P, P, 10, 1, 10, P, P, 10, None) == -10
+    assert L.te_server_poll(NULL, 1, None) == -1
+    assert L.te_server_wait(NULL, 1, None) == -1
+    assert L.te_server_times(NULL, 1, None, None, None) == -1
+    assert not L.te_server_create(0, -1, None)
+    assert not L.te_server_create(0, 65, None)
+    o = binding.te_opts()
+    o.coop_wgs = -2
+    assert not L.te_server_create(0, 1, ctypes.byref(o))
+    L.te_server_destroy(NULL)

@@ -172,6 +172,30 @@ def test_deterministic_repeat():
     assert np.array_equal(W1, W2) and np.array_equal(Z1, Z2)
 
 
+def test_chain_result_independent_of_group_size():
+    """The cooperative chain gives the same bits for any number of
+    workgroups (its group sums use one fixed order), so the plain, batched
+    and served paths agree exactly."""
+    n = 2000
+    d, e = G.laplacian_tridiag(n)
+    _say("group-size invariance, laplacian2000")
+    W0, Z0 = _gpu(d, e)
+    for wgs in (7, 64, 131):
+        W1, Z1, _ = B.tridiag_eigvecs_ex(d, e, 1, n, coop_wgs=wgs)
+        torch.cuda.synchronize()
+        assert np.array_equal(W1.cpu().numpy(), W0), wgs
+        assert np.array_equal(Z1.cpu().numpy().T, Z0), wgs
+    # two cooperative clusters sharing one launch (two groups): for n >= 1571
+    # the Laplacian is one cluster, and n^2 >= 2^20 entries go cooperative
+    probs = [G.laplacian_tridiag(1600), G.laplacian_tridiag(1800)]
+    out = B.tridiag_eigvecs_batched(probs)
+    torch.cuda.synchronize()
+    for (dd, ee), (W, Z) in zip(probs, out):
+        Wp, Zp = _gpu(dd, ee)
+        assert np.array_equal(W.cpu().numpy(), Wp)
+        assert np.array_equal(Z.cpu().numpy().T, Zp)
+
+
 def test_full_glued_7980_properties():
     d, e = G.workload_glued()
     _say("glued 7980 full")
