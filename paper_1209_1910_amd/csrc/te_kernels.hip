@@ -19,6 +19,18 @@ namespace te {
 // Small device helpers
 // ---------------------------------------------------------------------------
 
+// Pointers read from problem descriptors in memory are generic to the
+// compiler, which then emits flat memory instructions; those also count
+// against the LDS wait counter, so every LDS wait would drain them too.  All
+// of the library's buffers are global memory: say so once, where a pointer
+// enters a hot loop, and the global address space propagates to every use.
+template <class T>
+__device__ __forceinline__ T *as_global(T *p) {
+  return (T *)(__attribute__((address_space(1))) T *)p;
+}
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+
 __device__ __forceinline__ double wave_sum(double v) {
   // Fixed butterfly: every lane ends with the same, deterministic sum.
 #pragma unroll
@@ -543,6 +555,8 @@ __device__ inline Scr make_scr(double *base, int nmax, int mmax, int parity) {
 // a + lo and b + lo must have the same alignment modulo 16 bytes.
 __device__ __forceinline__ double wave_dot(const double *__restrict__ a, const double *__restrict__ b,
                                            int lo, int hi, int lane) {
+  a = as_global(a);
+  b = as_global(b);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (lo < hi && (reinterpret_cast<uintptr_t>(a + lo) & 15)) {
     if (lane == 0) a0 = a[lo] * b[lo];
@@ -573,6 +587,9 @@ __device__ __forceinline__ double wave_dot(const double *__restrict__ a, const d
 __device__ __forceinline__ void wave_dot2(const double *__restrict__ a, const double *__restrict__ b,
                                           const double *__restrict__ c, int len, int lane,
                                           double &ob, double &oc) {
+  a = as_global(a);
+  b = as_global(b);
+  c = as_global(c);
   double b0 = 0.0, b1 = 0.0, c0 = 0.0, c1 = 0.0;
   int lo = 0;
   if (len > 0 && (reinterpret_cast<uintptr_t>(a) & 15)) {
@@ -637,6 +654,7 @@ __device__ bool grp_sumsq(Ctx &c, const double *x, int i0, int n, double &out) {
   static_assert(NT >= kSumLanes, "group sums need 256 threads");
   constexpr int kStep = 8 * kSumLanes;
   __shared__ double s_p[kSumLanes / kWave];
+  x = as_global(x);
   if (!grp_sync<NT>(c)) return false;
   if (threadIdx.x < kSumLanes) {
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -675,6 +693,189 @@ struct CView {
   const unsigned char *Lswb;
 };
 
+// Back substitution x_i = y_i - a_i x_{i+1} - b_i x_{i+2} (a = u2/u1,
+// b = u3/u1 from the LU records, y = v on entry, x = v on exit), by one wave.
+// The recurrence is sequential and latency-bound, so it runs in lane 0 alone
+// (no broadcasts, no gathers): the wave stages 64-row blocks {a, b, y} from
+// the top into an LDS double buffer one block ahead, lane 0 keeps the LDS
+// reads kSweepRing rows ahead in a register ring (across block boundaries)
+// and stores each x to global memory through a per-block base pointer.
+constexpr int kSweepRing = 4;
+
+__device__ __forceinline__ void sweep_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CUR>
+__device__ __forceinline__ void sweep_block(const double4 (&rec)[2][kWave],
+                                            double4 (&ring)[kSweepRing], double &x1, double &x2,
+                                            gptr<double> xb) {
+#pragma unroll
+  for (int t = kWave - 1; t >= 0; t--) {
+    const int slot = (kWave - 1 - t) % kSweepRing;
+    const double4 c = ring[slot];
+    ring[slot] = (t - kSweepRing >= 0) ? rec[CUR][t - kSweepRing]
+                                       : rec[CUR ^ 1][t - kSweepRing + kWave];
+    const double x = fma(-c.x, x1, fma(-c.y, x2, c.z));
+    x2 = x1;
+    x1 = x;
+    xb[t] = x;
+  }
+}
+
+// Rows of the solution become final from the bottom; when `prog` is non-null
+// lane 0 publishes, each time a kSegRows-row segment (counted from row 0) is
+// complete, the word (seq << 32) | (rows final), after a device-scope release
+// of its stores, for consumers that overlap work with the sweep.
+constexpr int kSegRows = 1024;
+
+__device__ __forceinline__ void back_sweep(const double4 *R_, double *v_, int n, int lane,
+                                           unsigned long long *prog, unsigned long long seq) {
+  static_assert(kWave % kSweepRing == 0, "ring must tile a block");
+  int pub_next = ((n - 1) / kSegRows) * kSegRows;   // start of the next segment to publish
+  auto publish = [&](int done_lo) {                  // rows >= done_lo are final
+    if (!prog || done_lo > pub_next) return;
+    if (lane == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(prog, (seq << 32) | (unsigned long long)(n - done_lo), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    pub_next = done_lo > 0 ? ((done_lo - 1) / kSegRows) * kSegRows : -1;
+  };
+  // explicit global pointers: flat accesses would be drained by the LDS waits
+  const gptr<const double> rd = (gptr<const double>)(R_);   // record i at rd[4i .. 4i+3]
+  const gptr<double> v = (gptr<double>)v_;
+  __shared__ double4 rec[2][kWave];
+  const int nblk = (n + kWave - 1) / kWave;
+  // block k holds rows n - 64 (k + 1) + j, j = 0..63 (rows below 0 are zero)
+  auto load = [&](int k) {
+    const int i = n - kWave * (k + 1) + lane;
+    double4 w = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (k < nblk && i >= 0) {
+      const size_t o = 4 * (size_t)i;
+      w = make_double4(rd[o + 2], rd[o + 3], v[i], 0.0);   // {u2/u1, u3/u1, y}
+    }
+    return w;
+  };
+  rec[0][lane] = load(0);
+  double4 pf = load(1);
+  sweep_wave_sync();
+  double x1 = 0.0, x2 = 0.0;
+  double4 ring[kSweepRing];
+#pragma unroll
+  for (int d = 0; d < kSweepRing; d++) ring[d] = rec[0][kWave - 1 - d];
+  const int nfull = (n % kWave == 0) ? nblk : nblk - 1;
+  int k = 0;
+  for (; k + 1 < nfull; k += 2) {
+    rec[1][lane] = pf;
+    pf = load(k + 2);
+    sweep_wave_sync();
+    if (lane == 0) sweep_block<0>(rec, ring, x1, x2, v + (n - kWave * (k + 1)));
+    sweep_wave_sync();
+    publish(n - kWave * (k + 1));
+    rec[0][lane] = pf;
+    pf = load(k + 3);
+    sweep_wave_sync();
+    if (lane == 0) sweep_block<1>(rec, ring, x1, x2, v + (n - kWave * (k + 2)));
+    sweep_wave_sync();
+    publish(n - kWave * (k + 2));
+  }
+  if (k < nfull) {  // one more full block, in buffer 0
+    rec[1][lane] = pf;
+    pf = load(k + 2);
+    sweep_wave_sync();
+    if (lane == 0) sweep_block<0>(rec, ring, x1, x2, v + (n - kWave * (k + 1)));
+    sweep_wave_sync();
+    publish(n - kWave * (k + 1));
+    k++;
+  }
+  if (k < nblk) {  // the partial last block (rows 0 .. n mod 64 - 1), already staged
+    const int cur = k & 1;
+    if (lane == 0) {
+      const int base = n - kWave * (k + 1);
+      for (int t = kWave - 1; t >= 0 && base + t >= 0; t--) {
+        const double4 c = rec[cur][t];
+        const double x = fma(-c.x, x1, fma(-c.y, x2, c.z));
+        x2 = x1;
+        x1 = x;
+        v[base + t] = x;
+      }
+    }
+    sweep_wave_sync();
+    publish(0);
+  }
+}
+
+// P1 arithmetic, x_l = Y[:, l] . v over rows l..n-1 (column l of Y is zero
+// above row l), in kSegRows-row segments counted from row 0: each segment's
+// dot by one wave, the segments added from the bottom up.  The plain pass and
+// the pass overlapped with the back sweep produce the same bits.
+__device__ __forceinline__ double seg_dot(const double *col, const double *v, int l, int n, int s,
+                                          int lane) {
+  const int lo = s * kSegRows > l ? s * kSegRows : l;
+  const int hi = (s + 1) * kSegRows < n ? (s + 1) * kSegRows : n;
+  return wave_dot(col, v, lo, hi, lane);
+}
+
+__device__ __forceinline__ double col_dot_segmented(const double *col, const double *v, int l,
+                                                    int n, int lane) {
+  const int top = (n - 1) / kSegRows;
+  double acc = 0.0;
+  for (int s = top; s >= l / kSegRows; s--) {
+    const double d = seg_dot(col, v, l, n, s, lane);
+    acc = (s == top) ? d : acc + d;
+  }
+  return acc;
+}
+
+// The next iteration's P1 (x = Y_c^T v) computed while rank 0 runs the back
+// sweep: the workgroups of ranks 1..size-1 take the columns, follow the
+// sweep's published progress segment by segment (thread 0 polls, then an
+// acquire), and accumulate each column in x[l] (owned by one wave).
+// Returns false on abort.
+template <int NT>
+__device__ bool p1_overlapped(Ctx &cx, const CView &cv, int c, const double *v, double *x,
+                              const unsigned long long *prog, unsigned long long seq) {
+  const int n = cv.n;
+  const int top = (n - 1) / kSegRows;
+  const int gw = (cx.rank - 1) * (NT / kWave) + cx.wave;
+  const int nw = (cx.size - 1) * (NT / kWave);
+  __shared__ int s_go;
+  for (int s = top; s >= 0; s--) {
+    if (threadIdx.x == 0) {
+      const unsigned long long target = (seq << 32) | (unsigned long long)(n - s * kSegRows);
+      int ok = 1;
+      unsigned long long spins = 0;
+      while (__hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        if ((++spins & 255ull) == 0) {
+          if (__hip_atomic_load(cx.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ok = 0;
+            break;
+          }
+          if (spins > kSpinLimit) {
+            __hip_atomic_store(cx.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = 0;
+            break;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_go = ok;
+    }
+    __syncthreads();
+    if (!s_go) return false;
+    for (int l = gw; l < c; l += nw) {
+      if (s < l / kSegRows) continue;   // segment above row l
+      const double d = seg_dot(cv.Y + (size_t)l * cv.ldy, v, l, n, s, cx.lane);
+      if (cx.lane == 0) x[l] = (s == top) ? d : x[l] + d;
+    }
+  }
+  return true;
+}
+
 // Solve (T - lambda I) v = q/||q|| with the stored LU of member c, spread over
 // the whole group.  rn = 1/||q|| comes from the pass that produced q.
 //  S1  every wave scans 64-row chunks of the affine maps
@@ -683,21 +884,22 @@ struct CView {
 //  S2  every workgroup scans the chunk summaries for the carries into each
 //      chunk (in LDS) and forms y'_i = y_i / u1_i for its own rows;
 //  S3  the back sweep x_i = y'_i - (u2/u1)_i x_{i+1} - (u3/u1)_i x_{i+2}
-//      runs sequentially in wave 0 of rank 0 (a blocked version of it is not
-//      stable), 64 rows per staged block with two blocks in flight.
+//      runs sequentially in lane 0 of wave 0 of rank 0 (a blocked version of
+//      it is not stable); see back_sweep.
 // Returns false on abort.
 constexpr int kLdsCarries = 2048;
 
 template <int NT>
 __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restrict__ q,
-                          double *__restrict__ v, const Scr &S, double rn) {
+                          double *__restrict__ v, const Scr &S, double rn, bool overlap_p1) {
   const int n = cv.n;
   const int tid = threadIdx.x, lane = cx.lane, wave = cx.wave;
   const int gtid = cx.rank * NT + tid, gthreads = cx.size * NT;
-  const double4 *__restrict__ R = cv.Lrec + (size_t)c * n;
-  const unsigned char *__restrict__ SW = cv.Lswb + (size_t)c * n;
+  const double4 *__restrict__ R = as_global(cv.Lrec + (size_t)c * n);
+  const unsigned char *__restrict__ SW = as_global(cv.Lswb + (size_t)c * n);
+  q = as_global(q);
+  v = as_global(v);
   __shared__ double s_carry[kLdsCarries + 1];
-  __shared__ double st_u2[kWave], st_u3[kWave], st_y[kWave], st_x[kWave];
 
   // S1: chunk scans
   const int nmaps = n - 1;
@@ -766,57 +968,14 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
   }
   if (!grp_sync<NT>(cx)) return false;
 
-  // S3: back substitution
-  if (cx.rank == 0 && wave == 0) {
-    double x1 = 0.0, x2 = 0.0;
-    int hi = n;
-    int lo = hi - kWave > 0 ? hi - kWave : 0;
-    int lo1 = lo - kWave > 0 ? lo - kWave : 0;
-    double pu2 = 0.0, pu3 = 0.0, py = 0.0, qu2 = 0.0, qu3 = 0.0, qy = 0.0;
-    if (lo + lane < hi) {
-      const double4 r = R[lo + lane];
-      pu2 = r.z; pu3 = r.w; py = v[lo + lane];
-    }
-    if (lo > 0 && lo1 + lane < lo) {
-      const double4 r = R[lo1 + lane];
-      qu2 = r.z; qu3 = r.w; qy = v[lo1 + lane];
-    }
-    while (hi > 0) {
-      st_u2[lane] = pu2; st_u3[lane] = pu3; st_y[lane] = py;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      pu2 = qu2; pu3 = qu3; py = qy;
-      const int lo2 = lo1 - kWave > 0 ? lo1 - kWave : 0;
-      if (lo1 > 0 && lo2 + lane < lo1) {
-        const double4 r = R[lo2 + lane];
-        qu2 = r.z; qu3 = r.w; qy = v[lo2 + lane];
-      }
-      if (hi - lo == kWave) {
-#pragma unroll
-        for (int tt = kWave - 1; tt >= 0; tt--) {
-          const double x = fma(-st_u2[tt], x1, fma(-st_u3[tt], x2, st_y[tt]));
-          x2 = x1;
-          x1 = x;
-          st_x[tt] = x;
-        }
-      } else {
-        for (int tt = hi - lo - 1; tt >= 0; tt--) {
-          const double x = fma(-st_u2[tt], x1, fma(-st_u3[tt], x2, st_y[tt]));
-          x2 = x1;
-          x1 = x;
-          st_x[tt] = x;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (lo + lane < hi) v[lo + lane] = st_x[lane];
-      __builtin_amdgcn_wave_barrier();
-      hi = lo;
-      lo = lo1;
-      lo1 = lo2;
-    }
+  // S3: back substitution, one lane of one wave; with overlap_p1 (groups of
+  // two or more workgroups) the other ranks compute the next P1 meanwhile.
+  unsigned long long *prog = reinterpret_cast<unsigned long long *>(cx.cnt + 24);
+  const unsigned long long seq = cx.gen;
+  if (cx.rank == 0) {
+    if (wave == 0) back_sweep(R, v, n, lane, overlap_p1 ? prog : nullptr, seq);
+  } else if (overlap_p1) {
+    if (!p1_overlapped<NT>(cx, cv, c, v, S.x, prog, seq)) return false;
   }
   return grp_sync<NT>(cx);
 }
@@ -830,14 +989,14 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
   cv.n = P.n; cv.M = it.size;
   cv.ldy = (size_t)P.ldy;
   cv.ldm = (size_t)P.ldm;
-  cv.Y = P.Y + s0 * cv.ldy;
-  cv.Yr = P.Yr + s0;
-  cv.T = P.T + s0 + s0 * cv.ldm;
-  cv.Tr = P.Tr + s0 + s0 * cv.ldm;
-  cv.Z = P.Z + s0 * P.ldz;
+  cv.Y = as_global(P.Y + s0 * cv.ldy);
+  cv.Yr = as_global(P.Yr + s0);
+  cv.T = as_global(P.T + s0 + s0 * cv.ldm);
+  cv.Tr = as_global(P.Tr + s0 + s0 * cv.ldm);
+  cv.Z = as_global(P.Z + s0 * P.ldz);
   cv.ldz = (size_t)P.ldz;
-  cv.Lrec = reinterpret_cast<const double4 *>(P.Lrec) + s0 * P.n;
-  cv.Lswb = P.Lswb + s0 * P.n;
+  cv.Lrec = as_global(reinterpret_cast<const double4 *>(P.Lrec) + s0 * P.n);
+  cv.Lswb = as_global(P.Lswb + s0 * P.n);
   const int n = cv.n;
   const size_t ldy = cv.ldy, ldm = cv.ldm;
   const int tid = threadIdx.x, lane = cx.lane;
@@ -868,14 +1027,19 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
   }
 
   const double *vin = S.v;
+  const bool overlap_p1 = cx.size > 1;
+  bool x_ready = false;   // P1 already done beside the last back sweep
   for (int c = 1; c < cv.M; c++) {
     for (int k = 1; k <= iters; k++) {
       // P1: x = Y_c^T v
-      for (int l = cx.gw; l < c; l += cx.nw) {
-        const double acc = wave_dot(cv.Y + (size_t)l * ldy, vin, l, n, lane);
-        if (lane == 0) S.x[l] = acc;
+      if (!x_ready) {
+        for (int l = cx.gw; l < c; l += cx.nw) {
+          const double acc = col_dot_segmented(cv.Y + (size_t)l * ldy, vin, l, n, lane);
+          if (lane == 0) S.x[l] = acc;
+        }
+        if (!grp_sync<NT>(cx)) return false;
       }
-      if (!grp_sync<NT>(cx)) return false;
+      x_ready = false;
       // P2: x' = T_c^T x (column l has l + 1 entries: folded assignment)
       for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
         const int l = fold_index(cx.gw, cx.nw, t, c);
@@ -954,7 +1118,8 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         // P7: next iterate v = (T - lambda I)^{-1} q / ||q||
         double qn2;
         if (!grp_sumsq<NT>(cx, S.q, 0, n, qn2)) return false;
-        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(qn2))) return false;
+        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(qn2), overlap_p1)) return false;
+        x_ready = overlap_p1;
       }
     }
   }
@@ -975,7 +1140,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chain_small(const Prob *__res
   cx.abort_flag = nullptr;
   cx.wave = threadIdx.x / kWave; cx.lane = threadIdx.x % kWave;
   cx.gw = cx.wave; cx.nw = kSmallThreads / kWave;
-  double *base = scr.base + (size_t)blockIdx.x * scr.stride;
+  double *base = as_global(scr.base + (size_t)blockIdx.x * scr.stride);
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
@@ -1024,7 +1189,7 @@ __global__ void __launch_bounds__(kCoopThreads) k_chain_coop(const Prob *__restr
   cx.lane = threadIdx.x % kWave;
   cx.gw = cx.rank * (kCoopThreads / kWave) + cx.wave;
   cx.nw = cx.size * (kCoopThreads / kWave);
-  double *base = scr.base + (size_t)g * scr.stride;
+  double *base = as_global(scr.base + (size_t)g * scr.stride);
   for (int q = 0; q < G.nit; q++) {
     const ChainItem it = items[G.it0 + q];
     const Prob &P = probs[it.prob];
