@@ -550,32 +550,38 @@ __device__ inline Scr make_scr(double *base, int nmax, int mmax, int parity) {
   return S;
 }
 
-// Dot product of a[lo..hi) and b[lo..hi) by one wave: 16-byte loads, eight
-// in flight per lane, fixed combination order; every lane gets the sum.
-// a + lo and b + lo must have the same alignment modulo 16 bytes.
-__device__ __forceinline__ double wave_dot(const double *__restrict__ a, const double *__restrict__ b,
-                                           int lo, int hi, int lane) {
-  a = as_global(a);
-  b = as_global(b);
+// Native two-double vector and global-memory pointer types for the dot
+// products: loads through address-space-1 pointers compile to global (not
+// flat) instructions, so the compiler can wait on them one group at a time.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) d2v *gd2p;
+typedef const __attribute__((address_space(1))) double *gdp;
+
+// Dot product of a[lo..hi) and b[lo..hi) by one wave: 16-byte loads, fixed
+// combination order; every lane gets the sum.  a + lo and b + lo must have
+// the same alignment modulo 16 bytes.
+__device__ __forceinline__ double wave_dot(const double *a_, const double *b_, int lo, int hi,
+                                           int lane) {
+  const gdp a = (gdp)a_, b = (gdp)b_;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (lo < hi && (reinterpret_cast<uintptr_t>(a + lo) & 15)) {
+  if (lo < hi && (reinterpret_cast<uintptr_t>(a_ + lo) & 15)) {
     if (lane == 0) a0 = a[lo] * b[lo];
     lo++;
   }
   const int np = (hi - lo) >> 1;
-  const double2 *__restrict__ A2 = reinterpret_cast<const double2 *>(a + lo);
-  const double2 *__restrict__ B2 = reinterpret_cast<const double2 *>(b + lo);
+  const gd2p A2 = (gd2p)(a + lo);
+  const gd2p B2 = (gd2p)(b + lo);
   int p = lane;
   for (; p + 3 * kWave < np; p += 4 * kWave) {
-    const double2 x0 = A2[p], x1 = A2[p + kWave], x2 = A2[p + 2 * kWave], x3 = A2[p + 3 * kWave];
-    const double2 y0 = B2[p], y1 = B2[p + kWave], y2 = B2[p + 2 * kWave], y3 = B2[p + 3 * kWave];
+    const d2v x0 = A2[p], x1 = A2[p + kWave], x2 = A2[p + 2 * kWave], x3 = A2[p + 3 * kWave];
+    const d2v y0 = B2[p], y1 = B2[p + kWave], y2 = B2[p + 2 * kWave], y3 = B2[p + 3 * kWave];
     a0 = fma(x0.x, y0.x, a0); a0 = fma(x0.y, y0.y, a0);
     a1 = fma(x1.x, y1.x, a1); a1 = fma(x1.y, y1.y, a1);
     a2 = fma(x2.x, y2.x, a2); a2 = fma(x2.y, y2.y, a2);
     a3 = fma(x3.x, y3.x, a3); a3 = fma(x3.y, y3.y, a3);
   }
   for (; p < np; p += kWave) {
-    const double2 x0 = A2[p], y0 = B2[p];
+    const d2v x0 = A2[p], y0 = B2[p];
     a0 = fma(x0.x, y0.x, a0); a0 = fma(x0.y, y0.y, a0);
   }
   if (((hi - lo) & 1) && lane == 0) a1 = fma(a[hi - 1], b[hi - 1], a1);
@@ -584,34 +590,31 @@ __device__ __forceinline__ double wave_dot(const double *__restrict__ a, const d
 
 // Two dot products sharing the matrix row a: (a.b, a.c) over [0, len); a, b
 // and c must have the same alignment modulo 16 bytes.
-__device__ __forceinline__ void wave_dot2(const double *__restrict__ a, const double *__restrict__ b,
-                                          const double *__restrict__ c, int len, int lane,
-                                          double &ob, double &oc) {
-  a = as_global(a);
-  b = as_global(b);
-  c = as_global(c);
+__device__ __forceinline__ void wave_dot2(const double *a_, const double *b_, const double *c_,
+                                          int len, int lane, double &ob, double &oc) {
+  const gdp a = (gdp)a_, b = (gdp)b_, c = (gdp)c_;
   double b0 = 0.0, b1 = 0.0, c0 = 0.0, c1 = 0.0;
   int lo = 0;
-  if (len > 0 && (reinterpret_cast<uintptr_t>(a) & 15)) {
+  if (len > 0 && (reinterpret_cast<uintptr_t>(a_) & 15)) {
     if (lane == 0) { b0 = a[0] * b[0]; c0 = a[0] * c[0]; }
     lo = 1;
   }
   const int np = (len - lo) >> 1;
-  const double2 *__restrict__ A2 = reinterpret_cast<const double2 *>(a + lo);
-  const double2 *__restrict__ B2 = reinterpret_cast<const double2 *>(b + lo);
-  const double2 *__restrict__ C2 = reinterpret_cast<const double2 *>(c + lo);
+  const gd2p A2 = (gd2p)(a + lo);
+  const gd2p B2 = (gd2p)(b + lo);
+  const gd2p C2 = (gd2p)(c + lo);
   int p = lane;
   for (; p + kWave < np; p += 2 * kWave) {
-    const double2 m0 = A2[p], m1 = A2[p + kWave];
-    const double2 y0 = B2[p], y1 = B2[p + kWave];
-    const double2 z0 = C2[p], z1 = C2[p + kWave];
+    const d2v m0 = A2[p], m1 = A2[p + kWave];
+    const d2v y0 = B2[p], y1 = B2[p + kWave];
+    const d2v z0 = C2[p], z1 = C2[p + kWave];
     b0 = fma(m0.x, y0.x, b0); b0 = fma(m0.y, y0.y, b0);
     c0 = fma(m0.x, z0.x, c0); c0 = fma(m0.y, z0.y, c0);
     b1 = fma(m1.x, y1.x, b1); b1 = fma(m1.y, y1.y, b1);
     c1 = fma(m1.x, z1.x, c1); c1 = fma(m1.y, z1.y, c1);
   }
   for (; p < np; p += kWave) {
-    const double2 m0 = A2[p], y0 = B2[p], z0 = C2[p];
+    const d2v m0 = A2[p], y0 = B2[p], z0 = C2[p];
     b0 = fma(m0.x, y0.x, b0); b0 = fma(m0.y, y0.y, b0);
     c0 = fma(m0.x, z0.x, c0); c0 = fma(m0.y, z0.y, c0);
   }
