@@ -80,7 +80,7 @@ struct ChainScratch {
 };
 
 size_t chain_scratch_doubles(int nmax, int mmax, int nwg_in_group);
-constexpr size_t kBarWords = 32;     // unsigned words of barrier state per group
+constexpr size_t kBarWords = 64;     // unsigned words of barrier state per group
 
 // Launch helpers (te_kernels.hip).  Multi-problem kernels map a flat lane
 // index t to (problem b, index j) through loff (nprob + 1 prefix offsets).

@@ -31,6 +31,18 @@ __device__ __forceinline__ T *as_global(T *p) {
 template <class T>
 using gptr = __attribute__((address_space(1))) T *;
 
+// Store of data that other workgroups read after a group barrier: a relaxed
+// device-scope atomic store, which writes through to the device coherence
+// point instead of leaving a dirty line in this XCD's L2.  Measured: with
+// plain stores, a barrier whose single thread-0 release follows the other
+// waves' stores let those stores be missed now and then when two groups
+// shared the device (results then differed in the last bits), and a release
+// in every wave instead cost 40 % of the chain's time.
+template <class T>
+__device__ __forceinline__ void st_dev(T *p, T v) {
+  __hip_atomic_store((gptr<T>)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   // Fixed butterfly: every lane ends with the same, deterministic sum.
 #pragma unroll
@@ -468,12 +480,23 @@ struct Ctx {
   unsigned *cnt;       // group arrival counter (unused when size == 1)
   unsigned *flag;      // group release flag: last completed generation
   unsigned gen;        // generation of the next barrier
+  unsigned sgen;       // generation of the next barrier among ranks 1..size-1
   int *abort_flag;
   int gw, nw;          // wave index in the group, waves in the group
   int wave, lane;
 };
 
 constexpr unsigned long long kSpinLimit = 1ull << 24;  // only a broken run waits that long
+// s_waitcnt immediate (gfx9 encoding): vmcnt = 0, expcnt = 7, lgkmcnt = 15.
+constexpr int kWaitVmcnt0 = (0x7 << 4) | (0xF << 8);
+
+// Device-scope acquire by one thread on behalf of its workgroup: the cache
+// invalidation it issues must have completed before the workgroup barrier
+// lets the other waves load, or their loads can still hit stale L2 lines.
+__device__ __forceinline__ void wg_acquire() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+}
 
 // Group barrier: arrive on the counter; the last arrival publishes the
 // generation on the flag; the others poll the flag.  Returns false (in every
@@ -481,6 +504,12 @@ constexpr unsigned long long kSpinLimit = 1ull << 24;  // only a broken run wait
 // limit sets the abort flag, so every workgroup of every group unwinds.
 template <int NT>
 __device__ bool grp_sync(Ctx &c) {
+  // Every wave waits for its own stores to complete before the workgroup
+  // arrives: the workgroup barrier alone does not, and a store still in
+  // flight could reach this XCD's L2 after thread 0's writeback (the device
+  // release below) and stay invisible to the other XCDs.  (s_waitcnt with
+  // vmcnt 0 and the other counters at their maximum.)
+  if (c.size > 1) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
   if (c.size == 1) return true;
   __shared__ int s_ok;
@@ -502,7 +531,7 @@ __device__ bool grp_sync(Ctx &c) {
         }
       }
     }
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    wg_acquire();
     s_ok = ok;
   }
   __syncthreads();
@@ -517,13 +546,18 @@ struct Scr {
   double *x, *xp, *s, *r, *xpp;    // mmax + 2 each (offset by the start parity)
   double *carry;                   // n / 64 + 8: carries into the scan chunks
   double *csum;                    // 2 (n / 64) + 16: chunk summaries (A, B)
+  // next member's first-iteration products (lookahead)
+  double *vla, *upre;              // n each (even offsets)
+  double *xla, *xpla;              // mmax + 2 each (offset by the start parity)
+  double *xseg;                    // n / 1024 + 2: segment partials of one column dot
 };
 
 __host__ __device__ inline size_t even_up(size_t x) { return (x + 1) & ~(size_t)1; }
 
 __host__ __device__ inline size_t scr_doubles(int nmax, int mmax) {
-  return even_up(5 * even_up((size_t)nmax) + 5 * even_up((size_t)mmax + 2) +
-                 even_up((size_t)nmax / 64 + 8) + even_up(2 * ((size_t)nmax / 64) + 16) + 64);
+  return even_up(7 * even_up((size_t)nmax) + 7 * even_up((size_t)mmax + 2) +
+                 even_up((size_t)nmax / 64 + 8) + even_up(2 * ((size_t)nmax / 64) + 16) +
+                 even_up((size_t)nmax / 1024 + 2) + 64);
 }
 
 size_t chain_scratch_doubles(int nmax, int mmax, int nwg_in_group) {
@@ -546,7 +580,12 @@ __device__ inline Scr make_scr(double *base, int nmax, int mmax, int parity) {
   S.r = p + parity; p += mm;
   S.xpp = p + parity; p += mm;
   S.carry = p; p += even_up((size_t)nmax / 64 + 8);
-  S.csum = p;
+  S.csum = p; p += even_up(2 * ((size_t)nmax / 64) + 16);
+  S.vla = p; p += nn;
+  S.upre = p; p += nn;
+  S.xla = p + parity; p += mm;
+  S.xpla = p + parity; p += mm;
+  S.xseg = p;
   return S;
 }
 
@@ -865,7 +904,7 @@ __device__ bool p1_overlapped(Ctx &cx, const CView &cv, int c, const double *v, 
           }
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      wg_acquire();
       s_go = ok;
     }
     __syncthreads();
@@ -873,10 +912,65 @@ __device__ bool p1_overlapped(Ctx &cx, const CView &cv, int c, const double *v, 
     for (int l = gw; l < c; l += nw) {
       if (s < l / kSegRows) continue;   // segment above row l
       const double d = seg_dot(cv.Y + (size_t)l * cv.ldy, v, l, n, s, cx.lane);
-      if (cx.lane == 0) x[l] = (s == top) ? d : x[l] + d;
+      if (cx.lane == 0) st_dev(&x[l], (s == top) ? d : x[l] + d);
     }
   }
   return true;
+}
+
+// Lookahead for member c + 1, run by ranks 1..size-1 while rank 0 does the
+// back sweep of member c's first iteration.  Member c + 1's first compact-WY
+// step needs, with v its raw first iterate (column c + 1 of Z):
+//   x_l = Y[:, l] . v, x'_l = T[0..l, l] . x, u_i = v_i - Yhat[i, :] x'.
+// Columns 0..c-1 of Y and T do not change while member c iterates, so
+//   vla = v, xla_l = x_l and xpla_l = x'_l for l < c, and
+//   upre_i = vla_i - Yhat[i, 0..c) . xpla for rows i > c
+// are computed here (barriers among the ranks taking part), in the same
+// arithmetic the plain passes use; the terms of column c follow once member c
+// is final.  The work is split over member c's two back sweeps (parts: bit 0
+// vla and xla, bit 1 xpla and upre) so that each fits beside its sweep.
+// Returns false on abort.
+template <int NT>
+__device__ bool lookahead(Ctx &cx, const CView &cv, int c, const Scr &S, int parts) {
+  Ctx sub = cx;
+  sub.rank = cx.rank - 1;
+  sub.size = cx.size - 1;
+  sub.cnt = cx.cnt + 32;
+  sub.flag = cx.cnt + 48;
+  sub.gen = cx.sgen;
+  sub.gw = sub.rank * (NT / kWave) + cx.wave;
+  sub.nw = sub.size * (NT / kWave);
+  const int n = cv.n, lane = cx.lane;
+  const int gtid = sub.rank * NT + (int)threadIdx.x, gthreads = sub.size * NT;
+  bool ok = true;
+  if (parts & 1) {
+    const double *zn = cv.Z + (size_t)(c + 1) * cv.ldz;
+    for (int i = gtid; i < n; i += gthreads) st_dev(&S.vla[i], zn[i]);
+    ok = grp_sync<NT>(sub);
+    if (ok) {
+      for (int l = sub.gw; l < c; l += sub.nw) {
+        const double acc = col_dot_segmented(cv.Y + (size_t)l * cv.ldy, S.vla, l, n, lane);
+        if (lane == 0) st_dev(&S.xla[l], acc);
+      }
+      if (parts & 2) ok = grp_sync<NT>(sub);
+    }
+  }
+  if (ok && (parts & 2)) {
+    for (int t = 0; fold_valid(sub.gw, sub.nw, t, c); t++) {
+      const int l = fold_index(sub.gw, sub.nw, t, c);
+      const double acc = wave_dot(cv.T + (size_t)l * cv.ldm, S.xla, 0, l + 1, lane);
+      if (lane == 0) st_dev(&S.xpla[l], acc);
+    }
+    ok = grp_sync<NT>(sub);
+    if (ok) {
+      for (int i = c + 1 + sub.gw; i < n; i += sub.nw) {
+        const double acc = wave_dot(cv.Yr + (size_t)i * cv.ldm, S.xpla, 0, c, lane);
+        if (lane == 0) st_dev(&S.upre[i], S.vla[i] - acc);
+      }
+    }
+  }
+  cx.sgen = sub.gen;
+  return ok;
 }
 
 // Solve (T - lambda I) v = q/||q|| with the stored LU of member c, spread over
@@ -894,7 +988,8 @@ constexpr int kLdsCarries = 2048;
 
 template <int NT>
 __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restrict__ q,
-                          double *__restrict__ v, const Scr &S, double rn, bool overlap_p1) {
+                          double *__restrict__ v, const Scr &S, double rn, bool overlap_p1,
+                          int la_parts) {
   const int n = cv.n;
   const int tid = threadIdx.x, lane = cx.lane, wave = cx.wave;
   const int gtid = cx.rank * NT + tid, gthreads = cx.size * NT;
@@ -922,8 +1017,8 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
       const double Bp = __shfl_up(B, off, kWave);
       if (lane >= off) { B = fma(A, Bp, B); A = A * Ap; }
     }
-    if (i < nmaps) { S.P[i] = A; S.Q[i] = B; }
-    if (lane == kWave - 1) { S.csum[2 * k] = A; S.csum[2 * k + 1] = B; }
+    if (i < nmaps) { st_dev(&S.P[i], A); st_dev(&S.Q[i], B); }
+    if (lane == kWave - 1) { st_dev(&S.csum[2 * k], A); st_dev(&S.csum[2 * k + 1], B); }
   }
   if (!grp_sync<NT>(cx)) return false;
 
@@ -945,14 +1040,14 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
       const double ck = lane == 0 ? cur : fma(Ae, cur, Be);
       if (k < nch) {
         if (in_lds) s_carry[k] = ck;
-        else S.carry[k] = ck;
+        else st_dev(&S.carry[k], ck);
       }
       const double Al = __shfl(A, kWave - 1, kWave), Bl = __shfl(B, kWave - 1, kWave);
       cur = fma(Al, cur, Bl);
     }
     if (lane == 0) {
       if (in_lds) s_carry[nch] = cur;
-      else S.carry[nch] = cur;
+      else st_dev(&S.carry[nch], cur);
     }
   }
   if (in_lds) {
@@ -967,17 +1062,19 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
     const double cur = (i % kWave == 0) ? ck : fma(S.P[i - 1], ck, S.Q[i - 1]);
     double y = cur;
     if (i < nmaps && SW[i]) y = q[i + 1] * rn;
-    v[i] = y * R[i].y;
+    st_dev(&v[i], y * R[i].y);
   }
   if (!grp_sync<NT>(cx)) return false;
 
   // S3: back substitution, one lane of one wave; with overlap_p1 (groups of
-  // two or more workgroups) the other ranks compute the next P1 meanwhile.
+  // two or more workgroups) the other ranks compute the next P1 meanwhile,
+  // after the lookahead parts la_parts for member c + 1.
   unsigned long long *prog = reinterpret_cast<unsigned long long *>(cx.cnt + 24);
   const unsigned long long seq = cx.gen;
   if (cx.rank == 0) {
     if (wave == 0) back_sweep(R, v, n, lane, overlap_p1 ? prog : nullptr, seq);
   } else if (overlap_p1) {
+    if (la_parts && !lookahead<NT>(cx, cv, c, S, la_parts)) return false;
     if (!p1_overlapped<NT>(cx, cv, c, v, S.x, prog, seq)) return false;
   }
   return grp_sync<NT>(cx);
@@ -1011,50 +1108,72 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
   {
     const double *z = cv.Z;
     const double *z1 = cv.Z + cv.ldz;
-    for (int i = gtid; i < n; i += gthreads) S.v[i] = z1[i];
+    for (int i = gtid; i < n; i += gthreads) st_dev(&S.v[i], z1[i]);
     double nz2;
     if (!grp_sumsq<NT>(cx, z, 0, n, nz2)) return false;
     const double z0 = z[0];
     const double g = -(z0 >= 0.0 ? 1.0 : -1.0) * sqrt(nz2);
     for (int i = gtid; i < n; i += gthreads) {
       const double y = (i == 0) ? z0 - g : z[i];
-      cv.Y[i] = y;
-      cv.Yr[(size_t)i * ldm] = y;
+      st_dev(&cv.Y[i], y);
+      st_dev(&cv.Yr[(size_t)i * ldm], y);
     }
     if (gtid == 0) {
       const double t = (g == 0.0) ? 0.0 : 1.0 / (g * g - z0 * g);
-      cv.T[0] = t;
-      cv.Tr[0] = t;
+      st_dev(&cv.T[0], t);
+      st_dev(&cv.Tr[0], t);
     }
     if (!grp_sync<NT>(cx)) return false;
   }
 
   const double *vin = S.v;
   const bool overlap_p1 = cx.size > 1;
+  // member c + 1's first step prepared during member c (needs a back sweep of
+  // member c to overlap with, hence iters >= 2, and a group to share it with)
+  const bool use_la = overlap_p1 && iters >= 2;
   bool x_ready = false;   // P1 already done beside the last back sweep
+  bool la_ready = false;  // this member's first step prepared by the lookahead
+  __shared__ double s_xpc;
   for (int c = 1; c < cv.M; c++) {
+    const bool la_next = use_la && c + 1 < cv.M;
+    const double *yprev = cv.Y + (size_t)(c - 1) * ldy;   // column c - 1 of Y
     for (int k = 1; k <= iters; k++) {
-      // P1: x = Y_c^T v
-      if (!x_ready) {
-        for (int l = cx.gw; l < c; l += cx.nw) {
-          const double acc = col_dot_segmented(cv.Y + (size_t)l * ldy, vin, l, n, lane);
-          if (lane == 0) S.x[l] = acc;
+      if (k == 1 && la_ready) {
+        // P1-P3 from the lookahead: x_{c-1} arrived with member c - 1's last
+        // step; x'_{c-1} = T[0..c-1, c-1] . x is formed by every workgroup
+        // (same bits everywhere); then u = upre - y_{c-1} x'_{c-1}.
+        if (cx.wave == 0) {
+          const double xpc = wave_dot(cv.T + (size_t)(c - 1) * ldm, S.xla, 0, c, lane);
+          if (lane == 0) s_xpc = xpc;
+        }
+        __syncthreads();
+        const double xpc = s_xpc;
+        for (int i = c + gtid; i < n; i += gthreads) st_dev(&S.u[i], S.upre[i] - yprev[i] * xpc);
+      } else {
+        // P1: x = Y_c^T v
+        if (!x_ready) {
+          for (int l = cx.gw; l < c; l += cx.nw) {
+            const double acc = col_dot_segmented(cv.Y + (size_t)l * ldy, vin, l, n, lane);
+            if (lane == 0) st_dev(&S.x[l], acc);
+          }
+          if (!grp_sync<NT>(cx)) return false;
+        }
+        // P2: x' = T_c^T x (column l has l + 1 entries: folded assignment)
+        for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
+          const int l = fold_index(cx.gw, cx.nw, t, c);
+          const double acc = wave_dot(cv.T + (size_t)l * ldm, S.x, 0, l + 1, lane);
+          if (lane == 0) st_dev(&S.xp[l], acc);
         }
         if (!grp_sync<NT>(cx)) return false;
+        // P3: u = v_hat - Yhat_c x' over rows c..n-1, the last column's term
+        // taken apart: u_i = (v_i - Yhat[i, 0..c-1) . x') - y_{c-1,i} x'_{c-1}
+        const double xpc = S.xp[c - 1];
+        for (int i = c + cx.gw; i < n; i += cx.nw) {
+          const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xp, 0, c - 1, lane);
+          if (lane == 0) st_dev(&S.u[i], (vin[i] - acc) - yprev[i] * xpc);
+        }
       }
       x_ready = false;
-      // P2: x' = T_c^T x (column l has l + 1 entries: folded assignment)
-      for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
-        const int l = fold_index(cx.gw, cx.nw, t, c);
-        const double acc = wave_dot(cv.T + (size_t)l * ldm, S.x, 0, l + 1, lane);
-        if (lane == 0) S.xp[l] = acc;
-      }
-      if (!grp_sync<NT>(cx)) return false;
-      // P3: u = v_hat - Yhat_c x' over rows c..n-1, and ||u||^2
-      for (int i = c + cx.gw; i < n; i += cx.nw) {
-        const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xp, 0, c, lane);
-        if (lane == 0) S.u[i] = vin[i] - acc;
-      }
       double beta2;
       if (!grp_sumsq<NT>(cx, S.u, c, n, beta2)) return false;
       // P4: Householder vector and s = Yhat_c^T y_hat
@@ -1068,63 +1187,84 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         const double acc = wave_dot(col, S.u, c + 1, n, lane);
         if (lane == 0) {
           const double rl = col[c];
-          S.s[l] = fma(rl, yc, acc);
-          S.r[l] = rl;
+          st_dev(&S.s[l], fma(rl, yc, acc));
+          st_dev(&S.r[l], rl);
         }
       }
       {
         double *ycol = cv.Y + (size_t)c * ldy;
         for (int i = c + gtid; i < n; i += gthreads) {
           const double y = (i == c) ? yc : S.u[i];
-          ycol[i] = y;
-          cv.Yr[(size_t)i * ldm + c] = y;
+          st_dev(&ycol[i], y);
+          st_dev(&cv.Yr[(size_t)i * ldm + c], y);
         }
         if (gtid == 0) {
-          cv.T[(size_t)c + (size_t)c * ldm] = tj;
-          cv.Tr[(size_t)c * ldm + c] = tj;
+          st_dev(&cv.T[(size_t)c + (size_t)c * ldm], tj);
+          st_dev(&cv.Tr[(size_t)c * ldm + c], tj);
         }
       }
       if (!grp_sync<NT>(cx)) return false;
+      const bool last = (k == iters);
       // P5: t_hat = -t_j T_c s (column c of T) and x'' = T_{c+1} r
-      // (row p has c - p entries: folded assignment)
+      // (row p has c - p entries: folded assignment).  Lookahead: the
+      // segment dots of x_c = Y[:, c] . vla for member c + 1, one wave each
+      // from the last wave down.
+      if (last && la_next) {
+        const int top = (n - 1) / kSegRows, s0 = c / kSegRows;
+        for (int sg = top - (cx.nw - 1 - cx.gw); sg >= s0; sg -= cx.nw) {
+          const double d = seg_dot(cv.Y + (size_t)c * ldy, S.vla, c, n, sg, lane);
+          if (lane == 0) st_dev(&S.xseg[sg], d);
+        }
+      }
       for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
         const int p = fold_index(cx.gw, cx.nw, t, c);
         double ts, tr;
         wave_dot2(cv.Tr + (size_t)p * ldm + p, S.s + p, S.r + p, c - p, lane, ts, tr);
         if (lane == 0) {
           const double th = -tj * ts;
-          cv.T[(size_t)p + (size_t)c * ldm] = th;
-          cv.Tr[(size_t)p * ldm + c] = th;
-          S.xpp[p] = fma(th, yc, tr);
+          st_dev(&cv.T[(size_t)p + (size_t)c * ldm], th);
+          st_dev(&cv.Tr[(size_t)p * ldm + c], th);
+          st_dev(&S.xpp[p], fma(th, yc, tr));
         }
       }
-      if (gtid == 0) S.xpp[c] = tj * yc;
+      if (gtid == 0) st_dev(&S.xpp[c], tj * yc);
       if (!grp_sync<NT>(cx)) return false;
       // P6: q = Y_{c+1} x'' - e_c; after the last step, also stage the next
       // member's raw first iterate into the aligned scratch v.  Rows below c
-      // are shorter (min(i, c) + 1 entries): folded assignment.
-      const bool last = (k == iters);
+      // are shorter (min(i, c) + 1 entries): folded assignment.  Lookahead:
+      // the last wave adds the segment dots of x_c bottom-up (the order of
+      // col_dot_segmented).
+      if (last && la_next && cx.gw == cx.nw - 1 && lane == 0) {
+        const int top = (n - 1) / kSegRows, s0 = c / kSegRows;
+        double acc = S.xseg[top];
+        for (int sg = top - 1; sg >= s0; sg--) acc = acc + S.xseg[sg];
+        st_dev(&S.xla[c], acc);
+      }
       double *qout = last ? (cv.Z + (size_t)c * cv.ldz) : S.q;
       for (int t = 0; fold_valid(cx.gw, cx.nw, t, n); t++) {
         const int i = fold_index(cx.gw, cx.nw, t, n);
         const int l1 = (i < c ? i : c) + 1;
         const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xpp, 0, l1, lane);
-        if (lane == 0) qout[i] = (i == c) ? acc - 1.0 : acc;
+        if (lane == 0) st_dev(&qout[i], (i == c) ? acc - 1.0 : acc);
       }
       if (last) {
         if (c + 1 < cv.M) {
           const double *zn = cv.Z + (size_t)(c + 1) * cv.ldz;
-          for (int i = gtid; i < n; i += gthreads) S.v[i] = zn[i];
+          for (int i = gtid; i < n; i += gthreads) st_dev(&S.v[i], zn[i]);
         }
         if (!grp_sync<NT>(cx)) return false;
       } else {
         // P7: next iterate v = (T - lambda I)^{-1} q / ||q||
         double qn2;
         if (!grp_sumsq<NT>(cx, S.q, 0, n, qn2)) return false;
-        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(qn2), overlap_p1)) return false;
+        // lookahead parts: both in the first sweep if there is only one
+        const int la_parts = !la_next ? 0 : (k == 1 ? (iters >= 3 ? 1 : 3) : (k == 2 ? 2 : 0));
+        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(qn2), overlap_p1, la_parts))
+          return false;
         x_ready = overlap_p1;
       }
     }
+    la_ready = la_next;
   }
   return true;
 }
@@ -1139,7 +1279,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chain_small(const Prob *__res
                                                                ChainScratch scr, int iters) {
   __shared__ int s_item;
   Ctx cx;
-  cx.rank = 0; cx.size = 1; cx.cnt = nullptr; cx.flag = nullptr; cx.gen = 0;
+  cx.rank = 0; cx.size = 1; cx.cnt = nullptr; cx.flag = nullptr; cx.gen = 0; cx.sgen = 0;
   cx.abort_flag = nullptr;
   cx.wave = threadIdx.x / kWave; cx.lane = threadIdx.x % kWave;
   cx.gw = cx.wave; cx.nw = kSmallThreads / kWave;
@@ -1167,7 +1307,9 @@ hipError_t launch_chain_small(const Prob *probs, const ChainItem *items, int nit
 
 // Large clusters: cooperative launch; workgroup w belongs to group
 // wg_group[w] and runs that group's items in order with group barriers.
-// bars holds two counters per group, 64 bytes apart: arrivals, release flag.
+// bars holds kBarWords words per group: arrivals (word 0), release flag (16),
+// back-sweep progress (24-25), and the lookahead sub-group's arrivals (32) and
+// release flag (48).
 __global__ void __launch_bounds__(kCoopThreads) k_chain_coop(const Prob *__restrict__ probs,
                                                              const ChainItem *__restrict__ items,
                                                              const Group *__restrict__ groups,
@@ -1184,9 +1326,10 @@ __global__ void __launch_bounds__(kCoopThreads) k_chain_coop(const Prob *__restr
   Ctx cx;
   cx.rank = (int)blockIdx.x - G.wg0;
   cx.size = G.nwg;
-  cx.cnt = bars + (size_t)g * 32;
-  cx.flag = bars + (size_t)g * 32 + 16;
+  cx.cnt = bars + (size_t)g * kBarWords;
+  cx.flag = bars + (size_t)g * kBarWords + 16;
   cx.gen = 0;
+  cx.sgen = 0;
   cx.abort_flag = abort_flag;
   cx.wave = threadIdx.x / kWave;
   cx.lane = threadIdx.x % kWave;

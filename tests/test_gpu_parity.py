@@ -186,14 +186,17 @@ def test_chain_result_independent_of_group_size():
         assert np.array_equal(W1.cpu().numpy(), W0), wgs
         assert np.array_equal(Z1.cpu().numpy().T, Z0), wgs
     # two cooperative clusters sharing one launch (two groups): for n >= 1571
-    # the Laplacian is one cluster, and n^2 >= 2^20 entries go cooperative
+    # the Laplacian is one cluster, and n^2 >= 2^20 entries go cooperative.
+    # Repeated: concurrent groups once exposed writes that a group barrier
+    # did not publish (results then differed in the last bits now and then).
     probs = [G.laplacian_tridiag(1600), G.laplacian_tridiag(1800)]
-    out = B.tridiag_eigvecs_batched(probs)
-    torch.cuda.synchronize()
-    for (dd, ee), (W, Z) in zip(probs, out):
-        Wp, Zp = _gpu(dd, ee)
-        assert np.array_equal(W.cpu().numpy(), Wp)
-        assert np.array_equal(Z.cpu().numpy().T, Zp)
+    plain = [_gpu(dd, ee) for dd, ee in probs]
+    for rep in range(6):
+        out = B.tridiag_eigvecs_batched(probs)
+        torch.cuda.synchronize()
+        for (Wp, Zp), (W, Z) in zip(plain, out):
+            assert np.array_equal(W.cpu().numpy(), Wp), rep
+            assert np.array_equal(Z.cpu().numpy().T, Zp), rep
 
 
 def test_full_glued_7980_properties():
