@@ -504,11 +504,12 @@ __device__ __forceinline__ void wg_acquire() {
 // limit sets the abort flag, so every workgroup of every group unwinds.
 template <int NT>
 __device__ bool grp_sync(Ctx &c) {
-  // Every wave waits for its own stores to complete before the workgroup
-  // arrives: the workgroup barrier alone does not, and a store still in
-  // flight could reach this XCD's L2 after thread 0's writeback (the device
-  // release below) and stay invisible to the other XCDs.  (s_waitcnt with
-  // vmcnt 0 and the other counters at their maximum.)
+  // Arrival.  Everything other workgroups read after a group barrier is
+  // written with write-through (device-scope) stores, and the back sweep
+  // releases its own stores when it publishes progress; so arriving only
+  // needs every wave's stores to have completed (s_waitcnt vmcnt 0, the
+  // other counters at their maximum), and the counter and flag updates can
+  // be relaxed: no L2 writeback per barrier.
   if (c.size > 1) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
   if (c.size == 1) return true;
@@ -516,9 +517,9 @@ __device__ bool grp_sync(Ctx &c) {
   c.gen++;
   if (threadIdx.x == 0) {
     int ok = 1;
-    const unsigned old = __hip_atomic_fetch_add(c.cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned old = __hip_atomic_fetch_add(c.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old + 1u == c.gen * (unsigned)c.size)
-      __hip_atomic_store(c.flag, c.gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(c.flag, c.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long spins = 0;
     while (__hip_atomic_load(c.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < c.gen) {
       __builtin_amdgcn_s_sleep(1);
