@@ -320,6 +320,25 @@ void SharedHold::release() {
 
 namespace {
 
+// Library-owned workspace blocks of one call: freed on every return path.
+// On an early (error) return the stream is synchronized first, so that no
+// enqueued kernel still uses the memory when it is released.
+struct OwnedBlocks {
+  hipStream_t s;
+  std::vector<void *> blocks;
+  bool released = false;
+  explicit OwnedBlocks(hipStream_t st) : s(st) {}
+  ~OwnedBlocks() {
+    if (released || blocks.empty()) return;
+    (void)hipStreamSynchronize(s);
+    for (void *p : blocks) (void)hipFreeAsync(p, s);
+    (void)hipStreamSynchronize(s);
+    (void)hipGetLastError();
+  }
+  OwnedBlocks(const OwnedBlocks &) = delete;
+  OwnedBlocks &operator=(const OwnedBlocks &) = delete;
+};
+
 // Launch the cooperative chain kernel under the device gate (see DeviceGate)
 // and wait for it to complete.  The caller holds no shared hold and has
 // synchronized its stream.
@@ -407,8 +426,10 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   const size_t first_bytes = fixed_bytes(nprob) + per_prob;
   bool own = (ws == nullptr);
   char *base = static_cast<char *>(ws);
+  OwnedBlocks owned(stream);
   if (own) {
     TE_CHECK(hipMallocAsync((void **)&base, first_bytes, stream));
+    owned.blocks.push_back(base);
   } else if (ws_bytes < first_bytes) {
     return TE_ERR_WORKSPACE;
   }
@@ -539,6 +560,7 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   const size_t cbytes = chain_bytes(R.nmax, R.mmax, nslots, coop_nwg, nitems);
   if (own) {
     TE_CHECK(hipMallocAsync((void **)&cbase, cbytes, stream));
+    owned.blocks.push_back(cbase);
   } else {
     if (cv.off + cbytes > cv.cap) return TE_ERR_WORKSPACE;
     cbase = base + cv.off;
@@ -588,6 +610,7 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   TE_CHECK(hipStreamSynchronize(stream));
   tm.collect();
   if (own) {
+    owned.released = true;
     TE_CHECK(hipFreeAsync(cbase, stream));
     TE_CHECK(hipFreeAsync(base, stream));
     TE_CHECK(hipStreamSynchronize(stream));

@@ -213,6 +213,11 @@ struct te_server {
   Server s;
 };
 
+namespace {
+te_server *create_server(const DeviceLimits &lim, uint64_t hbm_budget, int lanes,
+                         const te_opts *opt);
+}  // namespace
+
 extern "C" {
 
 te_server *te_server_create(uint64_t hbm_budget, int lanes, const te_opts *opt) {
@@ -220,6 +225,19 @@ te_server *te_server_create(uint64_t hbm_budget, int lanes, const te_opts *opt) 
   if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0)) return nullptr;
   DeviceLimits lim = limits();
   if (lim.device < 0 || lim.coop <= 0 || lim.small <= 0) return nullptr;
+  try {
+    return create_server(lim, hbm_budget, lanes, opt);
+  } catch (...) {  // thread or memory exhaustion: no server
+    return nullptr;
+  }
+}
+
+}  // extern "C"
+
+namespace {
+
+te_server *create_server(const DeviceLimits &lim, uint64_t hbm_budget, int lanes,
+                         const te_opts *opt) {
   std::unique_ptr<te_server> h(new te_server);
   Server &S = h->s;
   S.device = lim.device;
@@ -239,9 +257,24 @@ te_server *te_server_create(uint64_t hbm_budget, int lanes, const te_opts *opt) 
     }
     S.streams.push_back(st);
   }
-  for (int k = 0; k < nl; k++) S.lanes.emplace_back([&S, k] { S.lane_main(k); });
+  try {
+    for (int k = 0; k < nl; k++) S.lanes.emplace_back([&S, k] { S.lane_main(k); });
+  } catch (...) {  // stop the lanes that did start, then give up
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      S.stop = true;
+    }
+    S.cv.notify_all();
+    for (auto &t : S.lanes) t.join();
+    for (hipStream_t x : S.streams) (void)hipStreamDestroy(x);
+    throw;
+  }
   return h.release();
 }
+
+}  // namespace
+
+extern "C" {
 
 int te_server_submit(te_server *srv, const double *d, const double *e, int n, int il, int iu,
                      double *W, double *Z, int ldz, int64_t *id) {

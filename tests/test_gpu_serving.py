@@ -154,3 +154,27 @@ def test_requests_keep_arriving_while_busy(alone):
             W, Z = s.wait(rid)
             assert np.array_equal(W, ref[k][0]), k
             assert np.array_equal(Z, ref[k][1]), k
+
+
+def test_concurrent_submitters(alone):
+    """Several host threads submit to one server at once (the entry points
+    are thread-safe); every result is still the alone result."""
+    import threading
+    reqs, ref = alone
+    errors = []
+    with B.Server(lanes=3) as s:
+        def worker(t):
+            try:
+                for k in range(t, len(reqs), 3):
+                    d, e, il, iu = reqs[k]
+                    W, Z = s.wait(s.submit(d, e, il, iu))
+                    if not (np.array_equal(W, ref[k][0]) and np.array_equal(Z, ref[k][1])):
+                        errors.append(k)
+            except Exception as exc:  # surfaced below
+                errors.append(repr(exc))
+        threads = [threading.Thread(target=worker, args=(t,)) for t in range(3)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+    assert not errors, errors
