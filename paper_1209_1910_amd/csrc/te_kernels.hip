@@ -974,16 +974,19 @@ __device__ bool lookahead(Ctx &cx, const CView &cv, int c, const Scr &S, int par
   return ok;
 }
 
-// Solve (T - lambda I) v = q/||q|| with the stored LU of member c, spread over
-// the whole group.  rn = 1/||q|| comes from the pass that produced q.
-//  S1  every wave scans 64-row chunks of the affine maps
+// Solve (T - lambda I) v = q/||q|| with the stored LU of member c.  The
+// forward sweep and the back sweep feed only each other, so rank 0 runs the
+// whole solve with workgroup barriers while the other ranks of the group do
+// overlapped work (next P1, lookahead); rn = 1/||q|| comes from the pass that
+// produced q.
+//  S1  the waves scan 64-row chunks of the affine maps
 //      cur_{i+1} = A_i cur_i + B_i of the forward sweep (|A_i| <= 1 under
 //      partial pivoting, so the scan is as stable as the recurrence);
-//  S2  every workgroup scans the chunk summaries for the carries into each
-//      chunk (in LDS) and forms y'_i = y_i / u1_i for its own rows;
+//  S2  wave 0 scans the chunk summaries for the carries into each chunk
+//      (in LDS), then the workgroup forms y'_i = y_i / u1_i;
 //  S3  the back sweep x_i = y'_i - (u2/u1)_i x_{i+1} - (u3/u1)_i x_{i+2}
-//      runs sequentially in lane 0 of wave 0 of rank 0 (a blocked version of
-//      it is not stable); see back_sweep.
+//      runs sequentially in lane 0 of wave 0 (a blocked version of it is
+//      not stable); see back_sweep.
 // Returns false on abort.
 constexpr int kLdsCarries = 2048;
 
@@ -993,79 +996,87 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
                           int la_parts) {
   const int n = cv.n;
   const int tid = threadIdx.x, lane = cx.lane, wave = cx.wave;
-  const int gtid = cx.rank * NT + tid, gthreads = cx.size * NT;
+  constexpr int NW = NT / kWave;
   const double4 *__restrict__ R = as_global(cv.Lrec + (size_t)c * n);
   const unsigned char *__restrict__ SW = as_global(cv.Lswb + (size_t)c * n);
   q = as_global(q);
   v = as_global(v);
   __shared__ double s_carry[kLdsCarries + 1];
 
-  // S1: chunk scans
-  const int nmaps = n - 1;
-  const int nch = (nmaps + kWave - 1) / kWave;
-  for (int k = cx.gw; k < nch; k += cx.nw) {
-    const int i = k * kWave + lane;
-    double A = 1.0, B = 0.0;
-    if (i < nmaps) {
-      const double bn = q[i + 1] * rn;
-      const double l = R[i].x;
-      if (SW[i]) { A = 1.0; B = -(l * bn); }
-      else { A = -l; B = bn; }
-    }
+  if (cx.rank == 0) {
+    // S1: chunk scans (chunk summaries in S.csum), two chunks per wave at a
+    // time so that their loads are in flight together
+    const int nmaps = n - 1;
+    const int nch = (nmaps + kWave - 1) / kWave;
+    constexpr int kBatch = 2;
+    for (int k0 = wave; k0 < nch; k0 += kBatch * NW) {
+      double A[kBatch], B[kBatch];
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const double Ap = __shfl_up(A, off, kWave);
-      const double Bp = __shfl_up(B, off, kWave);
-      if (lane >= off) { B = fma(A, Bp, B); A = A * Ap; }
-    }
-    if (i < nmaps) { st_dev(&S.P[i], A); st_dev(&S.Q[i], B); }
-    if (lane == kWave - 1) { st_dev(&S.csum[2 * k], A); st_dev(&S.csum[2 * k + 1], B); }
-  }
-  if (!grp_sync<NT>(cx)) return false;
-
-  // S2: carries into each chunk (scan of the chunk summaries, 64 at a time)
-  const bool in_lds = nch <= kLdsCarries;
-  if (in_lds ? (wave == 0) : (cx.rank == 0 && wave == 0)) {
-    double cur = q[0] * rn;
-    for (int k0 = 0; k0 < nch; k0 += kWave) {
-      const int k = k0 + lane;
-      double A = 1.0, B = 0.0;
-      if (k < nch) { A = S.csum[2 * k]; B = S.csum[2 * k + 1]; }
+      for (int u = 0; u < kBatch; u++) {
+        const int i = (k0 + u * NW) * kWave + lane;
+        A[u] = 1.0;
+        B[u] = 0.0;
+        if (k0 + u * NW < nch && i < nmaps) {
+          const double bn = q[i + 1] * rn;
+          const double l = R[i].x;
+          if (SW[i]) { B[u] = -(l * bn); }
+          else { A[u] = -l; B[u] = bn; }
+        }
+      }
 #pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-        const double Ap = __shfl_up(A, off, kWave);
-        const double Bp = __shfl_up(B, off, kWave);
-        if (lane >= off) { B = fma(A, Bp, B); A = A * Ap; }
+      for (int u = 0; u < kBatch; u++) {
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+          const double Ap = __shfl_up(A[u], off, kWave);
+          const double Bp = __shfl_up(B[u], off, kWave);
+          if (lane >= off) { B[u] = fma(A[u], Bp, B[u]); A[u] = A[u] * Ap; }
+        }
       }
-      const double Ae = __shfl_up(A, 1, kWave), Be = __shfl_up(B, 1, kWave);
-      const double ck = lane == 0 ? cur : fma(Ae, cur, Be);
-      if (k < nch) {
-        if (in_lds) s_carry[k] = ck;
-        else st_dev(&S.carry[k], ck);
+#pragma unroll
+      for (int u = 0; u < kBatch; u++) {
+        const int k = k0 + u * NW, i = k * kWave + lane;
+        if (k < nch) {
+          if (i < nmaps) { S.P[i] = A[u]; S.Q[i] = B[u]; }
+          if (lane == kWave - 1) { S.csum[2 * k] = A[u]; S.csum[2 * k + 1] = B[u]; }
+        }
       }
-      const double Al = __shfl(A, kWave - 1, kWave), Bl = __shfl(B, kWave - 1, kWave);
-      cur = fma(Al, cur, Bl);
     }
-    if (lane == 0) {
-      if (in_lds) s_carry[nch] = cur;
-      else st_dev(&S.carry[nch], cur);
-    }
-  }
-  if (in_lds) {
     __syncthreads();
-  } else if (!grp_sync<NT>(cx)) {
-    return false;
+
+    // S2: carries into each chunk (scan of the chunk summaries, 64 at a time)
+    const bool in_lds = nch <= kLdsCarries;
+    double *carry = in_lds ? s_carry : S.carry;
+    if (wave == 0) {
+      double cur = q[0] * rn;
+      for (int k0 = 0; k0 < nch; k0 += kWave) {
+        const int k = k0 + lane;
+        double A = 1.0, B = 0.0;
+        if (k < nch) { A = S.csum[2 * k]; B = S.csum[2 * k + 1]; }
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+          const double Ap = __shfl_up(A, off, kWave);
+          const double Bp = __shfl_up(B, off, kWave);
+          if (lane >= off) { B = fma(A, Bp, B); A = A * Ap; }
+        }
+        const double Ae = __shfl_up(A, 1, kWave), Be = __shfl_up(B, 1, kWave);
+        const double ck = lane == 0 ? cur : fma(Ae, cur, Be);
+        if (k < nch) carry[k] = ck;
+        const double Al = __shfl(A, kWave - 1, kWave), Bl = __shfl(B, kWave - 1, kWave);
+        cur = fma(Al, cur, Bl);
+      }
+      if (lane == 0) carry[nch] = cur;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) {
+      const int k = i / kWave;
+      const double ck = carry[k];
+      const double cur = (i % kWave == 0) ? ck : fma(S.P[i - 1], ck, S.Q[i - 1]);
+      double y = cur;
+      if (i < nmaps && SW[i]) y = q[i + 1] * rn;
+      v[i] = y * R[i].y;
+    }
+    __syncthreads();
   }
-  const double *carry = in_lds ? s_carry : S.carry;
-  for (int i = gtid; i < n; i += gthreads) {
-    const int k = i / kWave;
-    const double ck = carry[k];
-    const double cur = (i % kWave == 0) ? ck : fma(S.P[i - 1], ck, S.Q[i - 1]);
-    double y = cur;
-    if (i < nmaps && SW[i]) y = q[i + 1] * rn;
-    st_dev(&v[i], y * R[i].y);
-  }
-  if (!grp_sync<NT>(cx)) return false;
 
   // S3: back substitution, one lane of one wave; with overlap_p1 (groups of
   // two or more workgroups) the other ranks compute the next P1 meanwhile,
