@@ -30,6 +30,8 @@ __device__ __forceinline__ T *as_global(T *p) {
 }
 template <class T>
 using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+using lptr = __attribute__((address_space(3))) T *;
 
 // Store of data that other workgroups read after a group barrier: a relaxed
 // device-scope atomic store, which writes through to the device coherence
@@ -628,6 +630,49 @@ __device__ __forceinline__ double wave_dot(const double *a_, const double *b_, i
   return wave_sum((a0 + a1) + (a2 + a3));
 }
 
+// (a.b, a.c) over [lo, hi) with exactly wave_dot's arithmetic for each of the
+// two: one pass over a serves both products bit for bit.
+__device__ __forceinline__ void wave_dot_pair(const double *a_, const double *b_,
+                                              const double *c_, int lo, int hi, int lane,
+                                              double &ob, double &oc) {
+  const gdp a = (gdp)a_, b = (gdp)b_, c = (gdp)c_;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  if (lo < hi && (reinterpret_cast<uintptr_t>(a_ + lo) & 15)) {
+    if (lane == 0) { a0 = a[lo] * b[lo]; c0 = a[lo] * c[lo]; }
+    lo++;
+  }
+  const int np = (hi - lo) >> 1;
+  const gd2p A2 = (gd2p)(a + lo);
+  const gd2p B2 = (gd2p)(b + lo);
+  const gd2p C2 = (gd2p)(c + lo);
+  int p = lane;
+  for (; p + 3 * kWave < np; p += 4 * kWave) {
+    const d2v x0 = A2[p], x1 = A2[p + kWave], x2 = A2[p + 2 * kWave], x3 = A2[p + 3 * kWave];
+    const d2v y0 = B2[p], y1 = B2[p + kWave], y2 = B2[p + 2 * kWave], y3 = B2[p + 3 * kWave];
+    const d2v z0 = C2[p], z1 = C2[p + kWave], z2 = C2[p + 2 * kWave], z3 = C2[p + 3 * kWave];
+    a0 = fma(x0.x, y0.x, a0); a0 = fma(x0.y, y0.y, a0);
+    a1 = fma(x1.x, y1.x, a1); a1 = fma(x1.y, y1.y, a1);
+    a2 = fma(x2.x, y2.x, a2); a2 = fma(x2.y, y2.y, a2);
+    a3 = fma(x3.x, y3.x, a3); a3 = fma(x3.y, y3.y, a3);
+    c0 = fma(x0.x, z0.x, c0); c0 = fma(x0.y, z0.y, c0);
+    c1 = fma(x1.x, z1.x, c1); c1 = fma(x1.y, z1.y, c1);
+    c2 = fma(x2.x, z2.x, c2); c2 = fma(x2.y, z2.y, c2);
+    c3 = fma(x3.x, z3.x, c3); c3 = fma(x3.y, z3.y, c3);
+  }
+  for (; p < np; p += kWave) {
+    const d2v x0 = A2[p], y0 = B2[p], z0 = C2[p];
+    a0 = fma(x0.x, y0.x, a0); a0 = fma(x0.y, y0.y, a0);
+    c0 = fma(x0.x, z0.x, c0); c0 = fma(x0.y, z0.y, c0);
+  }
+  if (((hi - lo) & 1) && lane == 0) {
+    a1 = fma(a[hi - 1], b[hi - 1], a1);
+    c1 = fma(a[hi - 1], c[hi - 1], c1);
+  }
+  ob = wave_sum((a0 + a1) + (a2 + a3));
+  oc = wave_sum((c0 + c1) + (c2 + c3));
+}
+
 // Two dot products sharing the matrix row a: (a.b, a.c) over [0, len); a, b
 // and c must have the same alignment modulo 16 bytes.
 __device__ __forceinline__ void wave_dot2(const double *a_, const double *b_, const double *c_,
@@ -697,7 +742,7 @@ __device__ bool grp_sumsq(Ctx &c, const double *x, int i0, int n, double &out) {
   static_assert(NT >= kSumLanes, "group sums need 256 threads");
   constexpr int kStep = 8 * kSumLanes;
   __shared__ double s_p[kSumLanes / kWave];
-  x = as_global(x);
+  const gptr<const double> xg = (gptr<const double>)x;
   if (!grp_sync<NT>(c)) return false;
   if (threadIdx.x < kSumLanes) {
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -705,14 +750,14 @@ __device__ bool grp_sumsq(Ctx &c, const double *x, int i0, int n, double &out) {
     for (; i + 7 * kSumLanes < n; i += kStep) {
       double t[8];
 #pragma unroll
-      for (int r = 0; r < 8; r++) t[r] = x[i + r * kSumLanes];
+      for (int r = 0; r < 8; r++) t[r] = xg[i + r * kSumLanes];
 #pragma unroll
       for (int r = 0; r < 8; r++) a[r] = fma(t[r], t[r], a[r]);
     }
 #pragma unroll
     for (int r = 0; r < 7; r++) {
       const int ir = i + r * kSumLanes;
-      if (ir < n) a[r] = fma(x[ir], x[ir], a[r]);
+      if (ir < n) a[r] = fma(xg[ir], xg[ir], a[r]);
     }
     double p = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     p = wave_sum(p);
@@ -737,7 +782,8 @@ struct CView {
 };
 
 // Back substitution x_i = y_i - a_i x_{i+1} - b_i x_{i+2} (a = u2/u1,
-// b = u3/u1 from the LU records, y = v on entry, x = v on exit), by one wave.
+// b = u3/u1 from the LU records, y = y' formed while staging, x into v), by
+// one wave.
 // The recurrence is sequential and latency-bound, so it runs in lane 0 alone
 // (no broadcasts, no gathers): the wave stages 64-row blocks {a, b, y} from
 // the top into an LDS double buffer one block ahead, lane 0 keeps the LDS
@@ -774,7 +820,10 @@ __device__ __forceinline__ void sweep_block(const double4 (&rec)[2][kWave],
 // of its stores, for consumers that overlap work with the sweep.
 constexpr int kSegRows = 1024;
 
-__device__ __forceinline__ void back_sweep(const double4 *R_, double *v_, int n, int lane,
+__device__ __forceinline__ void back_sweep(const double4 *R_, const double *q_, double rn,
+                                           const double *P_, const double *Q_,
+                                           lptr<const double> carry_lds, const double *carry_glb,
+                                           const unsigned char *SW, double *v_, int n, int lane,
                                            unsigned long long *prog, unsigned long long seq) {
   static_assert(kWave % kSweepRing == 0, "ring must tile a block");
   int pub_next = ((n - 1) / kSegRows) * kSegRows;   // start of the next segment to publish
@@ -789,21 +838,51 @@ __device__ __forceinline__ void back_sweep(const double4 *R_, double *v_, int n,
   };
   // explicit global pointers: flat accesses would be drained by the LDS waits
   const gptr<const double> rd = (gptr<const double>)(R_);   // record i at rd[4i .. 4i+3]
+  const gptr<const double> q = (gptr<const double>)q_;
+  const gptr<const double> P = (gptr<const double>)P_;
+  const gptr<const double> Q = (gptr<const double>)Q_;
+  const gptr<const double> cg = (gptr<const double>)carry_glb;
+  const gptr<const unsigned char> sw = (gptr<const unsigned char>)SW;
   const gptr<double> v = (gptr<double>)v_;
   __shared__ double4 rec[2][kWave];
   const int nblk = (n + kWave - 1) / kWave;
   // block k holds rows n - 64 (k + 1) + j, j = 0..63 (rows below 0 are zero)
-  auto load = [&](int k) {
-    const int i = n - kWave * (k + 1) + lane;
-    double4 w = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (k < nblk && i >= 0) {
-      const size_t o = 4 * (size_t)i;
-      w = make_double4(rd[o + 2], rd[o + 3], v[i], 0.0);   // {u2/u1, u3/u1, y}
-    }
-    return w;
+  // y'_i = y_i / u1_i of the forward sweep, from the chunk scans: the carry
+  // into row i's chunk advanced by the chunk's prefix map (or, where rows
+  // were swapped, the right-hand side itself)
+  // The loads of a block are issued two blocks ahead and only combined when
+  // the block is staged, so their latency (the forward-scan values come from
+  // other workgroups' write-through stores) hides behind the sweep.
+  struct Raw {
+    double u, a, b, p, qq, qn;
+    int s;
   };
-  rec[0][lane] = load(0);
-  double4 pf = load(1);
+  auto row = [&](int k) { return (k < nblk) ? n - kWave * (k + 1) + lane : -1; };
+  auto load = [&](int k) {
+    Raw r;
+    const int i = row(k);
+    r.u = r.a = r.b = r.p = r.qq = r.qn = 0.0;
+    r.s = 0;
+    if (i >= 0) {
+      const size_t o = 4 * (size_t)i;
+      r.u = rd[o + 1];
+      r.a = rd[o + 2];
+      r.b = rd[o + 3];
+      if (i % kWave != 0) { r.p = P[i - 1]; r.qq = Q[i - 1]; }
+      if (i < n - 1) { r.qn = q[i + 1]; r.s = sw[i]; }
+    }
+    return r;
+  };
+  auto stage = [&](int k, const Raw &r) {     // {u2/u1, u3/u1, y'} of block k
+    const int i = row(k);
+    if (i < 0) return make_double4(0.0, 0.0, 0.0, 0.0);
+    const double ck = carry_lds ? carry_lds[i / kWave] : cg[i / kWave];
+    double y = (i % kWave == 0) ? ck : fma(r.p, ck, r.qq);
+    if (r.s) y = r.qn * rn;
+    return make_double4(r.a, r.b, y * r.u, 0.0);
+  };
+  rec[0][lane] = stage(0, load(0));
+  Raw pfa = load(1);
   sweep_wave_sync();
   double x1 = 0.0, x2 = 0.0;
   double4 ring[kSweepRing];
@@ -812,22 +891,21 @@ __device__ __forceinline__ void back_sweep(const double4 *R_, double *v_, int n,
   const int nfull = (n % kWave == 0) ? nblk : nblk - 1;
   int k = 0;
   for (; k + 1 < nfull; k += 2) {
-    rec[1][lane] = pf;
-    pf = load(k + 2);
+    rec[1][lane] = stage(k + 1, pfa);
+    pfa = load(k + 2);
     sweep_wave_sync();
     if (lane == 0) sweep_block<0>(rec, ring, x1, x2, v + (n - kWave * (k + 1)));
     sweep_wave_sync();
     publish(n - kWave * (k + 1));
-    rec[0][lane] = pf;
-    pf = load(k + 3);
+    rec[0][lane] = stage(k + 2, pfa);
+    pfa = load(k + 3);
     sweep_wave_sync();
     if (lane == 0) sweep_block<1>(rec, ring, x1, x2, v + (n - kWave * (k + 2)));
     sweep_wave_sync();
     publish(n - kWave * (k + 2));
   }
   if (k < nfull) {  // one more full block, in buffer 0
-    rec[1][lane] = pf;
-    pf = load(k + 2);
+    rec[1][lane] = stage(k + 1, pfa);
     sweep_wave_sync();
     if (lane == 0) sweep_block<0>(rec, ring, x1, x2, v + (n - kWave * (k + 1)));
     sweep_wave_sync();
@@ -876,11 +954,13 @@ __device__ __forceinline__ double col_dot_segmented(const double *col, const dou
 // The next iteration's P1 (x = Y_c^T v) computed while rank 0 runs the back
 // sweep: the workgroups of ranks 1..size-1 take the columns, follow the
 // sweep's published progress segment by segment (thread 0 polls, then an
-// acquire), and accumulate each column in x[l] (owned by one wave).
-// Returns false on abort.
+// acquire), and accumulate each column in x[l] (owned by one wave).  With v2
+// given, the same pass also accumulates x2_l = Y[:, l] . v2 (the lookahead's
+// products), from the same loads.  Returns false on abort.
 template <int NT>
 __device__ bool p1_overlapped(Ctx &cx, const CView &cv, int c, const double *v, double *x,
-                              const unsigned long long *prog, unsigned long long seq) {
+                              const double *v2, double *x2, const unsigned long long *prog,
+                              unsigned long long seq) {
   const int n = cv.n;
   const int top = (n - 1) / kSegRows;
   const int gw = (cx.rank - 1) * (NT / kWave) + cx.wave;
@@ -912,27 +992,39 @@ __device__ bool p1_overlapped(Ctx &cx, const CView &cv, int c, const double *v, 
     if (!s_go) return false;
     for (int l = gw; l < c; l += nw) {
       if (s < l / kSegRows) continue;   // segment above row l
-      const double d = seg_dot(cv.Y + (size_t)l * cv.ldy, v, l, n, s, cx.lane);
-      if (cx.lane == 0) st_dev(&x[l], (s == top) ? d : x[l] + d);
+      const double *col = cv.Y + (size_t)l * cv.ldy;
+      if (v2) {   // both products from one read of the column segment
+        const int lo = s * kSegRows > l ? s * kSegRows : l;
+        const int hi = (s + 1) * kSegRows < n ? (s + 1) * kSegRows : n;
+        double d, d2;
+        wave_dot_pair(col, v, v2, lo, hi, cx.lane, d, d2);
+        if (cx.lane == 0) {
+          st_dev(&x[l], (s == top) ? d : x[l] + d);
+          st_dev(&x2[l], (s == top) ? d2 : x2[l] + d2);
+        }
+      } else {
+        const double d = seg_dot(col, v, l, n, s, cx.lane);
+        if (cx.lane == 0) st_dev(&x[l], (s == top) ? d : x[l] + d);
+      }
     }
   }
   return true;
 }
 
 // Lookahead for member c + 1, run by ranks 1..size-1 while rank 0 does the
-// back sweep of member c's first iteration.  Member c + 1's first compact-WY
-// step needs, with v its raw first iterate (column c + 1 of Z):
+// back sweeps of member c.  Member c + 1's first compact-WY step needs, with
+// v its raw first iterate (column c + 1 of Z):
 //   x_l = Y[:, l] . v, x'_l = T[0..l, l] . x, u_i = v_i - Yhat[i, :] x'.
 // Columns 0..c-1 of Y and T do not change while member c iterates, so
 //   vla = v, xla_l = x_l and xpla_l = x'_l for l < c, and
 //   upre_i = vla_i - Yhat[i, 0..c) . xpla for rows i > c
-// are computed here (barriers among the ranks taking part), in the same
-// arithmetic the plain passes use; the terms of column c follow once member c
-// is final.  The work is split over member c's two back sweeps (parts: bit 0
-// vla and xla, bit 1 xpla and upre) so that each fits beside its sweep.
-// Returns false on abort.
+// are prepared in the same arithmetic the plain passes use (the terms of
+// column c follow once member c is final): in the first sweep vla is staged
+// and xla rides along the overlapped P1's reads of Y; in the second sweep
+// (or after the first, when there is only one) come xpla and upre.
+// Barriers here are among the ranks taking part.  Return false on abort.
 template <int NT>
-__device__ bool lookahead(Ctx &cx, const CView &cv, int c, const Scr &S, int parts) {
+__device__ Ctx la_sub(const Ctx &cx) {
   Ctx sub = cx;
   sub.rank = cx.rank - 1;
   sub.size = cx.size - 1;
@@ -941,52 +1033,54 @@ __device__ bool lookahead(Ctx &cx, const CView &cv, int c, const Scr &S, int par
   sub.gen = cx.sgen;
   sub.gw = sub.rank * (NT / kWave) + cx.wave;
   sub.nw = sub.size * (NT / kWave);
-  const int n = cv.n, lane = cx.lane;
+  return sub;
+}
+
+template <int NT>
+__device__ bool la_stage(Ctx &cx, const CView &cv, int c, const Scr &S) {
+  Ctx sub = la_sub<NT>(cx);
   const int gtid = sub.rank * NT + (int)threadIdx.x, gthreads = sub.size * NT;
-  bool ok = true;
-  if (parts & 1) {
-    const double *zn = cv.Z + (size_t)(c + 1) * cv.ldz;
-    for (int i = gtid; i < n; i += gthreads) st_dev(&S.vla[i], zn[i]);
-    ok = grp_sync<NT>(sub);
-    if (ok) {
-      for (int l = sub.gw; l < c; l += sub.nw) {
-        const double acc = col_dot_segmented(cv.Y + (size_t)l * cv.ldy, S.vla, l, n, lane);
-        if (lane == 0) st_dev(&S.xla[l], acc);
-      }
-      if (parts & 2) ok = grp_sync<NT>(sub);
-    }
-  }
-  if (ok && (parts & 2)) {
+  const double *zn = cv.Z + (size_t)(c + 1) * cv.ldz;
+  for (int i = gtid; i < cv.n; i += gthreads) st_dev(&S.vla[i], zn[i]);
+  const bool ok = grp_sync<NT>(sub);
+  cx.sgen = sub.gen;
+  return ok;
+}
+
+template <int NT>
+__device__ bool la_tpass(Ctx &cx, const CView &cv, int c, const Scr &S, bool sync_first) {
+  Ctx sub = la_sub<NT>(cx);
+  const int n = cv.n, lane = cx.lane;
+  bool ok = !sync_first || grp_sync<NT>(sub);
+  if (ok) {
     for (int t = 0; fold_valid(sub.gw, sub.nw, t, c); t++) {
       const int l = fold_index(sub.gw, sub.nw, t, c);
       const double acc = wave_dot(cv.T + (size_t)l * cv.ldm, S.xla, 0, l + 1, lane);
       if (lane == 0) st_dev(&S.xpla[l], acc);
     }
     ok = grp_sync<NT>(sub);
-    if (ok) {
-      for (int i = c + 1 + sub.gw; i < n; i += sub.nw) {
-        const double acc = wave_dot(cv.Yr + (size_t)i * cv.ldm, S.xpla, 0, c, lane);
-        if (lane == 0) st_dev(&S.upre[i], S.vla[i] - acc);
-      }
+  }
+  if (ok) {
+    for (int i = c + 1 + sub.gw; i < n; i += sub.nw) {
+      const double acc = wave_dot(cv.Yr + (size_t)i * cv.ldm, S.xpla, 0, c, lane);
+      if (lane == 0) st_dev(&S.upre[i], S.vla[i] - acc);
     }
   }
   cx.sgen = sub.gen;
   return ok;
 }
 
-// Solve (T - lambda I) v = q/||q|| with the stored LU of member c.  The
-// forward sweep and the back sweep feed only each other, so rank 0 runs the
-// whole solve with workgroup barriers while the other ranks of the group do
-// overlapped work (next P1, lookahead); rn = 1/||q|| comes from the pass that
-// produced q.
-//  S1  the waves scan 64-row chunks of the affine maps
+// Solve (T - lambda I) v = q/||q|| with the stored LU of member c.
+// rn = 1/||q|| comes from the pass that produced q.
+//  S1  the waves of the group scan 64-row chunks of the affine maps
 //      cur_{i+1} = A_i cur_i + B_i of the forward sweep (|A_i| <= 1 under
 //      partial pivoting, so the scan is as stable as the recurrence);
-//  S2  wave 0 scans the chunk summaries for the carries into each chunk
-//      (in LDS), then the workgroup forms y'_i = y_i / u1_i;
+//  S2  wave 0 of rank 0 scans the chunk summaries for the carries into
+//      each chunk (in LDS);
 //  S3  the back sweep x_i = y'_i - (u2/u1)_i x_{i+1} - (u3/u1)_i x_{i+2}
-//      runs sequentially in lane 0 of wave 0 (a blocked version of it is
-//      not stable); see back_sweep.
+//      runs sequentially in lane 0 of wave 0 of rank 0 (a blocked version
+//      of it is not stable), forming y'_i = y_i / u1_i as it stages rows;
+//      see back_sweep.  Meanwhile the other ranks do overlapped work.
 // Returns false on abort.
 constexpr int kLdsCarries = 2048;
 
@@ -1003,49 +1097,38 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
   v = as_global(v);
   __shared__ double s_carry[kLdsCarries + 1];
 
-  if (cx.rank == 0) {
-    // S1: chunk scans (chunk summaries in S.csum), two chunks per wave at a
-    // time so that their loads are in flight together
-    const int nmaps = n - 1;
-    const int nch = (nmaps + kWave - 1) / kWave;
-    constexpr int kBatch = 2;
-    for (int k0 = wave; k0 < nch; k0 += kBatch * NW) {
-      double A[kBatch], B[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; u++) {
-        const int i = (k0 + u * NW) * kWave + lane;
-        A[u] = 1.0;
-        B[u] = 0.0;
-        if (k0 + u * NW < nch && i < nmaps) {
-          const double bn = q[i + 1] * rn;
-          const double l = R[i].x;
-          if (SW[i]) { B[u] = -(l * bn); }
-          else { A[u] = -l; B[u] = bn; }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; u++) {
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-          const double Ap = __shfl_up(A[u], off, kWave);
-          const double Bp = __shfl_up(B[u], off, kWave);
-          if (lane >= off) { B[u] = fma(A[u], Bp, B[u]); A[u] = A[u] * Ap; }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; u++) {
-        const int k = k0 + u * NW, i = k * kWave + lane;
-        if (k < nch) {
-          if (i < nmaps) { S.P[i] = A[u]; S.Q[i] = B[u]; }
-          if (lane == kWave - 1) { S.csum[2 * k] = A[u]; S.csum[2 * k + 1] = B[u]; }
-        }
-      }
+  // S1: chunk scans over the whole group (chunk summaries in S.csum)
+  const int nmaps = n - 1;
+  const int nch = (nmaps + kWave - 1) / kWave;
+  const gptr<const double> rd = (gptr<const double>)R;
+  const gptr<const unsigned char> sw = (gptr<const unsigned char>)SW;
+  const gptr<const double> qg = (gptr<const double>)q;
+  for (int k = cx.gw; k < nch; k += cx.nw) {
+    const int i = k * kWave + lane;
+    double A = 1.0, B = 0.0;
+    if (i < nmaps) {
+      const double bn = qg[i + 1] * rn;
+      const double l = rd[4 * (size_t)i];
+      if (sw[i]) { A = 1.0; B = -(l * bn); }
+      else { A = -l; B = bn; }
     }
-    __syncthreads();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const double Ap = __shfl_up(A, off, kWave);
+      const double Bp = __shfl_up(B, off, kWave);
+      if (lane >= off) { B = fma(A, Bp, B); A = A * Ap; }
+    }
+    if (i < nmaps) { st_dev(&S.P[i], A); st_dev(&S.Q[i], B); }
+    if (lane == kWave - 1) { st_dev(&S.csum[2 * k], A); st_dev(&S.csum[2 * k + 1], B); }
+  }
+  if (!grp_sync<NT>(cx)) return false;
 
+  // carries into the chunks: in LDS when they fit, else in the scratch slot
+  const bool lds_carry = nch <= kLdsCarries;
+  lptr<double> carry_lds = lds_carry ? (lptr<double>)s_carry : nullptr;
+  const gptr<double> carry_glb = (gptr<double>)S.carry;
+  if (cx.rank == 0) {
     // S2: carries into each chunk (scan of the chunk summaries, 64 at a time)
-    const bool in_lds = nch <= kLdsCarries;
-    double *carry = in_lds ? s_carry : S.carry;
     if (wave == 0) {
       double cur = q[0] * rn;
       for (int k0 = 0; k0 < nch; k0 += kWave) {
@@ -1060,34 +1143,40 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
         }
         const double Ae = __shfl_up(A, 1, kWave), Be = __shfl_up(B, 1, kWave);
         const double ck = lane == 0 ? cur : fma(Ae, cur, Be);
-        if (k < nch) carry[k] = ck;
+        if (k < nch) {
+          if (lds_carry) carry_lds[k] = ck;
+          else carry_glb[k] = ck;
+        }
         const double Al = __shfl(A, kWave - 1, kWave), Bl = __shfl(B, kWave - 1, kWave);
         cur = fma(Al, cur, Bl);
       }
-      if (lane == 0) carry[nch] = cur;
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += NT) {
-      const int k = i / kWave;
-      const double ck = carry[k];
-      const double cur = (i % kWave == 0) ? ck : fma(S.P[i - 1], ck, S.Q[i - 1]);
-      double y = cur;
-      if (i < nmaps && SW[i]) y = q[i + 1] * rn;
-      v[i] = y * R[i].y;
+      if (lane == 0) {
+        if (lds_carry) carry_lds[nch] = cur;
+        else carry_glb[nch] = cur;
+      }
     }
     __syncthreads();
   }
 
   // S3: back substitution, one lane of one wave; with overlap_p1 (groups of
   // two or more workgroups) the other ranks compute the next P1 meanwhile,
-  // after the lookahead parts la_parts for member c + 1.
+  // with the lookahead parts la_parts for member c + 1 (bit 0: stage vla, and
+  // xla from the same pass; bit 1: xpla and upre, ahead of the overlapped P1
+  // in a later sweep, after it when both parts share one sweep).
   unsigned long long *prog = reinterpret_cast<unsigned long long *>(cx.cnt + 24);
   const unsigned long long seq = cx.gen;
   if (cx.rank == 0) {
-    if (wave == 0) back_sweep(R, v, n, lane, overlap_p1 ? prog : nullptr, seq);
+    if (wave == 0)
+      back_sweep(R, q, rn, S.P, S.Q, carry_lds, S.carry, SW, v, n, lane,
+                 overlap_p1 ? prog : nullptr, seq);
   } else if (overlap_p1) {
-    if (la_parts && !lookahead<NT>(cx, cv, c, S, la_parts)) return false;
-    if (!p1_overlapped<NT>(cx, cv, c, v, S.x, prog, seq)) return false;
+    const bool la1 = la_parts & 1, la2 = la_parts & 2;
+    if (la1 && !la_stage<NT>(cx, cv, c, S)) return false;
+    if (la2 && !la1 && !la_tpass<NT>(cx, cv, c, S, false)) return false;
+    if (!p1_overlapped<NT>(cx, cv, c, v, S.x, la1 ? S.vla : nullptr, la1 ? S.xla : nullptr,
+                           prog, seq))
+      return false;
+    if (la2 && la1 && !la_tpass<NT>(cx, cv, c, S, true)) return false;
   }
   return grp_sync<NT>(cx);
 }
