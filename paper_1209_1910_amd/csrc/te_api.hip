@@ -583,7 +583,7 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   TE_CHECK(launch_fill_i32(dflags, 2, 0, stream));
   if (small_nwg > 0) {
     tm.begin(PH_SMALL);
-    TE_CHECK(launch_chain_small(R.dprobs, ditems, (int)small_items.size(), dflags + 1, scr,
+    TE_CHECK(launch_chain_small(R.dprobs, ditems, (int)small_items.size(), dflags + 1, dflags, scr,
                                 small_nwg, opt.iters, stream));
     tm.end();
   }

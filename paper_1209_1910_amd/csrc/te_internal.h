@@ -94,8 +94,8 @@ hipError_t launch_invit(const Prob *probs, int nprob, const int64_t *loff, int64
                         int iters, uint64_t seed, hipStream_t s);
 hipError_t launch_transpose(const Prob *probs, int nprob, int nmax, int mmax, hipStream_t s);
 hipError_t launch_chain_small(const Prob *probs, const ChainItem *items, int nitems,
-                              int *counter, ChainScratch scr, int nwg, int iters,
-                              hipStream_t s);
+                              int *counter, int *abort_flag, ChainScratch scr, int nwg,
+                              int iters, hipStream_t s);
 // started: null, or one host-coherent int per workgroup that the workgroup
 // sets to 1 when it begins (the host waits on it for residency).
 hipError_t launch_chain_coop(const Prob *probs, const ChainItem *items, const Group *groups,

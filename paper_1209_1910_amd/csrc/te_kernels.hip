@@ -781,33 +781,76 @@ struct CView {
   const unsigned char *Lswb;
 };
 
-// Back substitution x_i = y_i - a_i x_{i+1} - b_i x_{i+2} (a = u2/u1,
-// b = u3/u1 from the LU records, y = y' formed while staging, x into v), by
-// one wave.
-// The recurrence is sequential and latency-bound, so it runs in lane 0 alone
-// (no broadcasts, no gathers): the wave stages 64-row blocks {a, b, y} from
-// the top into an LDS double buffer one block ahead, lane 0 keeps the LDS
-// reads kSweepRing rows ahead in a register ring (across block boundaries)
-// and stores each x to global memory through a per-block base pointer.
+// Back substitution x_i = y'_i - a_i x_{i+1} - b_i x_{i+2} (a = u2/u1,
+// b = u3/u1 from the LU records, y' = y / u1 of the forward sweep, x into v).
+// The recurrence is sequential and latency-bound, so it runs in lane 0 of one
+// wave alone (no broadcasts, no gathers); everything else is taken off that
+// lane.  The workgroup's other waves (producers) form the rows {a, b, y'} in
+// 64-row blocks from the bottom up and stage them in an LDS ring of SLOTS
+// blocks, many blocks ahead, so global-memory latency never reaches the sweep
+// (consumer).  Lane 0 of the consumer keeps its LDS reads kSweepRing rows
+// ahead in a register ring (across block boundaries) and stores each x
+// through a per-block global base pointer.
 constexpr int kSweepRing = 4;
 
-__device__ __forceinline__ void sweep_wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// staged[s] = k + 1 once block k sits in slot s = k % SLOTS; freed = number
+// of blocks the consumer no longer reads; abort set by a wait that timed out.
+// Reset before every sweep (a workgroup barrier separates sweeps).
+struct alignas(16) SRow {
+  double a, b, y, pad;   // u2/u1, u3/u1, y'
+};
+
+template <int SLOTS>
+struct SweepRing {
+  SRow row[SLOTS][kWave];
+  int staged[SLOTS];
+  int freed;
+  int abort;
+};
+
+typedef const __attribute__((address_space(3))) SRow *ldrp;
+__device__ __forceinline__ SRow lds_row(ldrp p) {   // field by field: C++ copies are generic-only
+  SRow r;
+  r.a = p->a;
+  r.b = p->b;
+  r.y = p->y;
+  r.pad = 0.0;
+  return r;
+}
+constexpr unsigned kRingSpinLimit = 1u << 22;   // only a broken run waits that long
+
+// Whole-wave wait until the LDS word w reaches target; later LDS reads of
+// the wave see what the writer stored before it set w.  A wait past the spin
+// limit marks the ring aborted (and the run, through abort_flag); a marked
+// ring ends every other wait.
+__device__ __forceinline__ bool ring_wait(lptr<int> w, int target, lptr<int> ring_abort,
+                                          int *abort_flag) {
+  unsigned spins = 0;
+  while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+    if (__hip_atomic_load(ring_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+      return false;
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kRingSpinLimit) {
+      __hip_atomic_store(ring_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (abort_flag)
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  return true;
 }
 
-template <int CUR>
-__device__ __forceinline__ void sweep_block(const double4 (&rec)[2][kWave],
-                                            double4 (&ring)[kSweepRing], double &x1, double &x2,
-                                            gptr<double> xb) {
+// Sweep of one full block from LDS slot cur; the ring reads run on into the
+// next block's slot nxt.  x into xb[0..63].
+__device__ __forceinline__ void sweep_block(ldrp cur, ldrp nxt, SRow (&ring)[kSweepRing],
+                                            double &x1, double &x2, gptr<double> xb) {
 #pragma unroll
   for (int t = kWave - 1; t >= 0; t--) {
     const int slot = (kWave - 1 - t) % kSweepRing;
-    const double4 c = ring[slot];
-    ring[slot] = (t - kSweepRing >= 0) ? rec[CUR][t - kSweepRing]
-                                       : rec[CUR ^ 1][t - kSweepRing + kWave];
-    const double x = fma(-c.x, x1, fma(-c.y, x2, c.z));
+    const SRow c = ring[slot];
+    ring[slot] = lds_row((t - kSweepRing >= 0) ? cur + (t - kSweepRing) : nxt + (t - kSweepRing + kWave));
+    const double x = fma(-c.a, x1, fma(-c.b, x2, c.y));
     x2 = x1;
     x1 = x;
     xb[t] = x;
@@ -820,11 +863,11 @@ __device__ __forceinline__ void sweep_block(const double4 (&rec)[2][kWave],
 // of its stores, for consumers that overlap work with the sweep.
 constexpr int kSegRows = 1024;
 
-__device__ __forceinline__ void back_sweep(const double4 *R_, const double *q_, double rn,
-                                           const double *P_, const double *Q_,
-                                           lptr<const double> carry_lds, const double *carry_glb,
-                                           const unsigned char *SW, double *v_, int n, int lane,
-                                           unsigned long long *prog, unsigned long long seq) {
+// Consumer: the back sweep.  Block k holds rows n - 64 (k + 1) + j, j = 0..63
+// (rows below 0 are zero).  Returns false if a ring wait failed.
+template <int SLOTS>
+__device__ bool sweep_consume(SweepRing<SLOTS> &sr, double *v_, int n, int lane,
+                              unsigned long long *prog, unsigned long long seq, int *abort_flag) {
   static_assert(kWave % kSweepRing == 0, "ring must tile a block");
   int pub_next = ((n - 1) / kSegRows) * kSegRows;   // start of the next segment to publish
   auto publish = [&](int done_lo) {                  // rows >= done_lo are final
@@ -836,23 +879,66 @@ __device__ __forceinline__ void back_sweep(const double4 *R_, const double *q_, 
     }
     pub_next = done_lo > 0 ? ((done_lo - 1) / kSegRows) * kSegRows : -1;
   };
-  // explicit global pointers: flat accesses would be drained by the LDS waits
+  const gptr<double> v = (gptr<double>)v_;
+  const lptr<int> ab = (lptr<int>)&sr.abort;
+  const int nblk = (n + kWave - 1) / kWave;
+  const int nfull = (n % kWave == 0) ? nblk : nblk - 1;
+  if (!ring_wait((lptr<int>)&sr.staged[0], 1, ab, abort_flag)) return false;
+  if (nblk > 1 && !ring_wait((lptr<int>)&sr.staged[1 % SLOTS], 2, ab, abort_flag)) return false;
+  double x1 = 0.0, x2 = 0.0;
+  SRow ring[kSweepRing];
+#pragma unroll
+  for (int d = 0; d < kSweepRing; d++) ring[d] = lds_row((ldrp)sr.row[0] + (kWave - 1 - d));
+  int k = 0;
+  for (; k < nfull; k++) {
+    // the ring reads reach into block k + 1 (stale rows past the last block
+    // are read and never used)
+    if (k + 1 < nblk &&
+        !ring_wait((lptr<int>)&sr.staged[(k + 1) % SLOTS], k + 2, ab, abort_flag))
+      return false;
+    if (lane == 0)
+      sweep_block((ldrp)sr.row[k % SLOTS], (ldrp)sr.row[(k + 1) % SLOTS], ring, x1, x2,
+                  v + (n - kWave * (k + 1)));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    if (lane == 0) __hip_atomic_store((lptr<int>)&sr.freed, k + 1, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+    publish(n - kWave * (k + 1));
+  }
+  if (k < nblk) {  // the partial last block (rows 0 .. n mod 64 - 1), already waited for
+    if (lane == 0) {
+      const ldrp cur = (ldrp)sr.row[k % SLOTS];
+      const int base = n - kWave * (k + 1);
+      for (int t = kWave - 1; t >= 0 && base + t >= 0; t--) {
+        const SRow c = lds_row(cur + t);
+        const double x = fma(-c.a, x1, fma(-c.b, x2, c.y));
+        x2 = x1;
+        x1 = x;
+        v[base + t] = x;
+      }
+    }
+    publish(0);
+  }
+  return true;
+}
+
+// Producer p of np (one wave each): stages blocks p, p + np, ...  The row of
+// block k for lane j is i = n - 64 (k + 1) + j; its y'_i = y_i / u1_i comes
+// from the chunk scans: the carry into row i's chunk advanced by the chunk's
+// prefix map (or, where rows were swapped, the right-hand side itself).  The
+// loads of the producer's next block are issued before it waits for a slot.
+template <int SLOTS>
+__device__ bool sweep_produce(SweepRing<SLOTS> &sr, int p, int np, const double4 *R_,
+                              const double *q_, double rn, const double *P_, const double *Q_,
+                              lptr<const double> carry_lds, const double *carry_glb,
+                              const unsigned char *SW, int n, int lane, int *abort_flag) {
   const gptr<const double> rd = (gptr<const double>)(R_);   // record i at rd[4i .. 4i+3]
   const gptr<const double> q = (gptr<const double>)q_;
   const gptr<const double> P = (gptr<const double>)P_;
   const gptr<const double> Q = (gptr<const double>)Q_;
   const gptr<const double> cg = (gptr<const double>)carry_glb;
   const gptr<const unsigned char> sw = (gptr<const unsigned char>)SW;
-  const gptr<double> v = (gptr<double>)v_;
-  __shared__ double4 rec[2][kWave];
+  const lptr<int> ab = (lptr<int>)&sr.abort;
   const int nblk = (n + kWave - 1) / kWave;
-  // block k holds rows n - 64 (k + 1) + j, j = 0..63 (rows below 0 are zero)
-  // y'_i = y_i / u1_i of the forward sweep, from the chunk scans: the carry
-  // into row i's chunk advanced by the chunk's prefix map (or, where rows
-  // were swapped, the right-hand side itself)
-  // The loads of a block are issued two blocks ahead and only combined when
-  // the block is staged, so their latency (the forward-scan values come from
-  // other workgroups' write-through stores) hides behind the sweep.
   struct Raw {
     double u, a, b, p, qq, qn;
     int s;
@@ -873,60 +959,31 @@ __device__ __forceinline__ void back_sweep(const double4 *R_, const double *q_, 
     }
     return r;
   };
-  auto stage = [&](int k, const Raw &r) {     // {u2/u1, u3/u1, y'} of block k
+  Raw nx = load(p);
+  for (int k = p; k < nblk; k += np) {
+    const Raw r = nx;
+    nx = load(k + np);
+    // slot k % SLOTS last held block k - SLOTS
+    if (k >= SLOTS && !ring_wait((lptr<int>)&sr.freed, k - SLOTS + 1, ab, abort_flag))
+      return false;
     const int i = row(k);
-    if (i < 0) return make_double4(0.0, 0.0, 0.0, 0.0);
-    const double ck = carry_lds ? carry_lds[i / kWave] : cg[i / kWave];
-    double y = (i % kWave == 0) ? ck : fma(r.p, ck, r.qq);
-    if (r.s) y = r.qn * rn;
-    return make_double4(r.a, r.b, y * r.u, 0.0);
-  };
-  rec[0][lane] = stage(0, load(0));
-  Raw pfa = load(1);
-  sweep_wave_sync();
-  double x1 = 0.0, x2 = 0.0;
-  double4 ring[kSweepRing];
-#pragma unroll
-  for (int d = 0; d < kSweepRing; d++) ring[d] = rec[0][kWave - 1 - d];
-  const int nfull = (n % kWave == 0) ? nblk : nblk - 1;
-  int k = 0;
-  for (; k + 1 < nfull; k += 2) {
-    rec[1][lane] = stage(k + 1, pfa);
-    pfa = load(k + 2);
-    sweep_wave_sync();
-    if (lane == 0) sweep_block<0>(rec, ring, x1, x2, v + (n - kWave * (k + 1)));
-    sweep_wave_sync();
-    publish(n - kWave * (k + 1));
-    rec[0][lane] = stage(k + 2, pfa);
-    pfa = load(k + 3);
-    sweep_wave_sync();
-    if (lane == 0) sweep_block<1>(rec, ring, x1, x2, v + (n - kWave * (k + 2)));
-    sweep_wave_sync();
-    publish(n - kWave * (k + 2));
-  }
-  if (k < nfull) {  // one more full block, in buffer 0
-    rec[1][lane] = stage(k + 1, pfa);
-    sweep_wave_sync();
-    if (lane == 0) sweep_block<0>(rec, ring, x1, x2, v + (n - kWave * (k + 1)));
-    sweep_wave_sync();
-    publish(n - kWave * (k + 1));
-    k++;
-  }
-  if (k < nblk) {  // the partial last block (rows 0 .. n mod 64 - 1), already staged
-    const int cur = k & 1;
-    if (lane == 0) {
-      const int base = n - kWave * (k + 1);
-      for (int t = kWave - 1; t >= 0 && base + t >= 0; t--) {
-        const double4 c = rec[cur][t];
-        const double x = fma(-c.x, x1, fma(-c.y, x2, c.z));
-        x2 = x1;
-        x1 = x;
-        v[base + t] = x;
-      }
+    SRow w = {0.0, 0.0, 0.0, 0.0};
+    if (i >= 0) {
+      const double ck = carry_lds ? carry_lds[i / kWave] : cg[i / kWave];
+      double y = (i % kWave == 0) ? ck : fma(r.p, ck, r.qq);
+      if (r.s) y = r.qn * rn;
+      w = {r.a, r.b, y * r.u, 0.0};
     }
-    sweep_wave_sync();
-    publish(0);
+    __attribute__((address_space(3))) SRow *dst = (__attribute__((address_space(3))) SRow *)sr.row[k % SLOTS] + lane;
+    dst->a = w.a;
+    dst->b = w.b;
+    dst->y = w.y;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    if (lane == 0)
+      __hip_atomic_store((lptr<int>)&sr.staged[k % SLOTS], k + 1, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+  return true;
 }
 
 // P1 arithmetic, x_l = Y[:, l] . v over rows l..n-1 (column l of Y is zero
@@ -1079,8 +1136,9 @@ __device__ bool la_tpass(Ctx &cx, const CView &cv, int c, const Scr &S, bool syn
 //      each chunk (in LDS);
 //  S3  the back sweep x_i = y'_i - (u2/u1)_i x_{i+1} - (u3/u1)_i x_{i+2}
 //      runs sequentially in lane 0 of wave 0 of rank 0 (a blocked version
-//      of it is not stable), forming y'_i = y_i / u1_i as it stages rows;
-//      see back_sweep.  Meanwhile the other ranks do overlapped work.
+//      of it is not stable) while the other waves of rank 0 form
+//      y'_i = y_i / u1_i and stage the rows ahead of it (sweep_consume,
+//      sweep_produce).  Meanwhile the other ranks do overlapped work.
 // Returns false on abort.
 constexpr int kLdsCarries = 2048;
 
@@ -1096,6 +1154,8 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
   q = as_global(q);
   v = as_global(v);
   __shared__ double s_carry[kLdsCarries + 1];
+  constexpr int kSlots = NT >= 512 ? 16 : 8;
+  __shared__ SweepRing<kSlots> s_ring;
 
   // S1: chunk scans over the whole group (chunk summaries in S.csum)
   const int nmaps = n - 1;
@@ -1154,6 +1214,9 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
         if (lds_carry) carry_lds[nch] = cur;
         else carry_glb[nch] = cur;
       }
+    } else if (wave == 1) {   // reset the sweep ring (the last sweep ended at a barrier)
+      if (lane < kSlots) s_ring.staged[lane] = 0;
+      if (lane == 0) { s_ring.freed = 0; s_ring.abort = 0; }
     }
     __syncthreads();
   }
@@ -1166,9 +1229,16 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
   unsigned long long *prog = reinterpret_cast<unsigned long long *>(cx.cnt + 24);
   const unsigned long long seq = cx.gen;
   if (cx.rank == 0) {
+    // wave 0 sweeps, the other waves stage its rows; a failed ring wait
+    // marks the ring, and the workgroup leaves together
     if (wave == 0)
-      back_sweep(R, q, rn, S.P, S.Q, carry_lds, S.carry, SW, v, n, lane,
-                 overlap_p1 ? prog : nullptr, seq);
+      sweep_consume<kSlots>(s_ring, v, n, lane, overlap_p1 ? prog : nullptr, seq, cx.abort_flag);
+    else
+      sweep_produce<kSlots>(s_ring, wave - 1, NW - 1, R, q, rn, S.P, S.Q, carry_lds, S.carry, SW,
+                            n, lane, cx.abort_flag);
+    __syncthreads();
+    if (__hip_atomic_load((lptr<int>)&s_ring.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+      return false;
   } else if (overlap_p1) {
     const bool la1 = la_parts & 1, la2 = la_parts & 2;
     if (la1 && !la_stage<NT>(cx, cv, c, S)) return false;
@@ -1377,16 +1447,21 @@ constexpr int kCoopThreads = 512;
 __global__ void __launch_bounds__(kSmallThreads) k_chain_small(const Prob *__restrict__ probs,
                                                                const ChainItem *__restrict__ items,
                                                                int nitems, int *counter,
+                                                               int *abort_flag,
                                                                ChainScratch scr, int iters) {
   __shared__ int s_item;
   Ctx cx;
   cx.rank = 0; cx.size = 1; cx.cnt = nullptr; cx.flag = nullptr; cx.gen = 0; cx.sgen = 0;
-  cx.abort_flag = nullptr;
+  cx.abort_flag = abort_flag;
   cx.wave = threadIdx.x / kWave; cx.lane = threadIdx.x % kWave;
   cx.gw = cx.wave; cx.nw = kSmallThreads / kWave;
   double *base = as_global(scr.base + (size_t)blockIdx.x * scr.stride);
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    // after a failed run (abort flag set) no further items are taken
+    if (threadIdx.x == 0)
+      s_item = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                   ? nitems
+                   : atomicAdd(counter, 1);
     __syncthreads();
     const int idx = s_item;
     __syncthreads();
@@ -1399,10 +1474,11 @@ __global__ void __launch_bounds__(kSmallThreads) k_chain_small(const Prob *__res
 }
 
 hipError_t launch_chain_small(const Prob *probs, const ChainItem *items, int nitems, int *counter,
-                              ChainScratch scr, int nwg, int iters, hipStream_t s) {
+                              int *abort_flag, ChainScratch scr, int nwg, int iters,
+                              hipStream_t s) {
   if (nitems <= 0 || nwg <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_chain_small, dim3(nwg), dim3(kSmallThreads), 0, s, probs, items, nitems,
-                     counter, scr, iters);
+                     counter, abort_flag, scr, iters);
   return hipGetLastError();
 }
 
