@@ -101,44 +101,62 @@ def cpu_baseline(n_sample: int, n_target: int):
     }
 
 
-def batched_bench(count: int, plain_count: int) -> int:
+def batched_bench(count: int, plain_count: int, autotune: bool = True) -> int:
     """Batched workload: `count` independent problems (n log-uniform in
-    [64, 2048], 25 % glued Wilkinson), all eigenpairs.  Times one batched call
-    against plain one-problem-per-call runs of the same problems."""
+    [64, 2048], 25 % glued Wilkinson), all eigenpairs.  Times one launch of
+    the graph-captured batched path (chain configuration from the autotuner),
+    the host-planned batched call, and plain one-problem-per-call runs of the
+    same problems."""
     import numpy as np
     import torch
 
     from paper_1209_1910_amd import binding, inputs
 
     probs = inputs.batched_problems(count=count, seed=1)
-    ns = np.array([len(d) for d, _, _ in probs], dtype=np.int64)
-    off = np.zeros(count + 1, dtype=np.int64)
-    off[1:] = np.cumsum(ns)
-    woff = off[:-1].copy()
-    zsz = ns * ns
-    zoff = np.zeros(count, dtype=np.int64)
-    zoff[1:] = np.cumsum(zsz)[:-1]
-    dev = torch.device("cuda:0")
-    d_all = torch.from_numpy(np.concatenate([d for d, _, _ in probs])).to(dev)
-    e_all = torch.from_numpy(np.concatenate([e for _, e, _ in probs if len(e)])).to(dev)
-    W_all = torch.empty(int(ns.sum()), dtype=torch.float64, device=dev)
-    Z_all = torch.empty(int(zsz.sum()), dtype=torch.float64, device=dev)
-    il = np.ones(count, dtype=np.int32)
-    iu = ns.astype(np.int32)
+    lay = binding.BatchLayout([(d, e) for d, e, _ in probs], device="cuda:0")
+    ns = np.array(lay.ns, dtype=np.int64)
+    off, woff, zoff = lay.off, lay.woff, lay.zoff
+    d_all, e_all, W_all, Z_all = lay.d_all, lay.e_all, lay.W_all, lay.Z_all
     torch.cuda.synchronize()
     print(f"[bench] batched: {count} problems, sum n = {int(ns.sum())}", file=sys.stderr, flush=True)
-    binding.tridiag_eigvecs_batched_raw(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff)
+    binding.tridiag_eigvecs_batched(lay)
     torch.cuda.synchronize()
     print("[bench] batched warm-up done", file=sys.stderr, flush=True)
     binding.te_timing_reset()
     binding.te_timing_enable(True)
     t0 = time.perf_counter()
-    binding.tridiag_eigvecs_batched_raw(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff)
+    binding.tridiag_eigvecs_batched(lay)
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     binding.te_timing_enable(False)
     phases = binding.te_timing_read()
-    print(f"[bench] batched call {t_batched:.3f} s", file=sys.stderr, flush=True)
+    print(f"[bench] host-planned batched call {t_batched:.3f} s", file=sys.stderr, flush=True)
+    W_ref, Z_ref = W_all.clone(), Z_all.clone()
+
+    # graph-captured path: autotune on a sample, build, one warm-up launch, one timed launch
+    tune = None
+    if autotune:
+        t0 = time.perf_counter()
+        best, tried = binding.batch_autotune(lay)
+        tune = {"best": {"chain_threads": best[0], "chains_per_cu": best[1]},
+                "candidates_ms": {f"{c[0]}x{c[1]}": ms for c, ms in tried},
+                "tuning_s": time.perf_counter() - t0}
+        print(f"[bench] autotune: best {best}, {len(tried)} candidates", file=sys.stderr,
+              flush=True)
+    t0 = time.perf_counter()
+    g = binding.BatchGraph(lay)
+    t_build = time.perf_counter() - t0
+    info = g.info()
+    g.launch()
+    t0 = time.perf_counter()
+    g.launch()
+    t_graph = time.perf_counter() - t0
+    graph_equal = bool(torch.equal(W_all, W_ref) and torch.equal(Z_all, Z_ref))
+    g.close()
+    del W_ref, Z_ref
+    print(f"[bench] graph launch {t_graph:.3f} s (build {t_build:.2f} s), bit-identical "
+          f"{graph_equal}", file=sys.stderr, flush=True)
+    assert graph_equal, "graph path differs from the host-planned batched call"
 
     # plain path: one tridiag_eigvecs call per problem on the same stream
     pc = min(plain_count, count)
@@ -152,7 +170,7 @@ def batched_bench(count: int, plain_count: int) -> int:
             print(f"[bench] plain {b + 1}/{pc}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) * count / pc
-    # the same problems give the same eigenvalues and (up to rounding) eigenvectors
+    # the same problems give the same eigenvalues and eigenvectors
     for b in range(0, pc, max(1, pc // 64)):
         n = int(ns[b])
         W, Z = binding.tridiag_eigvecs(d_all[off[b]:off[b + 1]], e_all[eoff[b]:eoff[b] + n - 1])
@@ -161,21 +179,28 @@ def batched_bench(count: int, plain_count: int) -> int:
         Zb = Z_all[zoff[b]:zoff[b] + n * n].view(n, n)
         worst = max(worst, float((Z - Zb).abs().max()))
     out = {
-        "metric": "batched solves/s FP64 (plain one-problem-per-call path on the same GPU beside it)",
-        "value": count / t_batched,
+        "metric": "batched solves/s FP64, one hipGraph launch (plain one-problem-per-call path "
+                  "on the same GPU beside it)",
+        "value": count / t_graph,
         "unit": "solves/s",
         "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": 1000.0 * t_batched,
+        "ms_per_step": 1000.0 * t_graph,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{count} problems, n log-uniform [64, 2048] (seed 1), 25% glued "
                                "Wilkinson, all eigenpairs", "sum_n": int(ns.sum())},
+        "graph": {"solves_per_s": count / t_graph, "s": t_graph, "build_s": t_build,
+                  "chain_threads": info["chain_threads"], "chains_per_cu": info["chains_per_cu"],
+                  "segments": info["segments"], "device_bytes": info["device_bytes"],
+                  "bit_identical_to_host_planned": graph_equal, "autotune": tune},
+        "host_planned": {"solves_per_s": count / t_batched, "s": t_batched},
         "plain": {"solves_per_s": count / t_plain, "s_total": t_plain,
                   "calls_timed": pc, "extrapolated": pc < count},
-        "speedup_vs_plain": t_plain / t_batched,
+        "speedup_vs_plain": t_plain / t_graph,
+        "host_planned_speedup_vs_plain": t_plain / t_batched,
         "batched_vs_plain_max_dev": worst,
-        "phases_ms": {k: v[0] for k, v in phases.items()},
-        "phase_launches": {k: v[1] for k, v in phases.items()},
+        "phases_ms_host_planned": {k: v[0] for k, v in phases.items()},
+        "phase_launches_host_planned": {k: v[1] for k, v in phases.items()},
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -322,6 +347,8 @@ def main() -> int:
     ap.add_argument("--count", type=int, default=4096, help="batched: number of problems")
     ap.add_argument("--plain-count", type=int, default=4096,
                     help="batched: plain calls actually timed (rest extrapolated)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: skip the autotuner (table entry or default configuration)")
     ap.add_argument("--requests", type=int, default=60, help="serving: trace length")
     ap.add_argument("--qps", type=float, default=1.0, help="serving: arrival rate")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serving: HBM budget")
@@ -334,7 +361,7 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration()
     if args.workload == "batched":
-        return batched_bench(args.count, args.plain_count)
+        return batched_bench(args.count, args.plain_count, not args.no_autotune)
     if args.workload == "serving":
         return serving_bench(args.requests, args.qps, args.budget_gib, args.lanes)
 

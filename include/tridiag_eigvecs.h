@@ -125,6 +125,81 @@ int tridiag_eigvecs_batched(const double *d_all, const double *e_all, const int6
                             double *Z_all, const int64_t *zoff, int B, const te_opts *opt,
                             hipStream_t stream);
 
+/* ---- Graph-captured batched path ----
+ * The batched method with every step on the device, captured once into a
+ * hipGraph and then run by one graph launch per call.  The chain plan that
+ * tridiag_eigvecs_batched makes on the host (after reading the cluster tables
+ * back) is made here by device kernels: every cluster of two or more members
+ * becomes a chain, ordered by decreasing cost size^2 n, and a persistent
+ * kernel runs each chain in one workgroup.  Results are bit-identical to
+ * tridiag_eigvecs_batched and to tridiag_eigvecs problem by problem (the
+ * chains' sums have one fixed order whatever the workgroup size).  Since a
+ * chain never spreads over several workgroups here, this path suits batches of
+ * many moderate problems (the cooperative multi-workgroup chain of the other
+ * entry points is not used). */
+
+/* Launch configuration of the chain kernel of the graph path.
+ * chain_threads: threads per chain workgroup (256 or 512).
+ * chains_per_cu: resident chain workgroups per compute unit (1 .. the
+ * occupancy limit of that variant). */
+typedef struct te_graph_cfg {
+    int chain_threads;
+    int chains_per_cu;
+} te_graph_cfg;
+
+typedef struct te_batch_graph te_batch_graph;
+
+/* Build the graph for B problems laid out as for tridiag_eigvecs_batched (same
+ * arguments 1-11 with the same meaning and error positions).  The device
+ * pointers d_all, e_all, W_all, Z_all are captured: every launch reads the
+ * inputs they hold at that time and writes the outputs there.  cfg (argument
+ * 12) may be NULL: then the autotune table's entry for this batch's shape
+ * (see te_batch_autotune) is used, else {256, the occupancy limit}.
+ * Problems are grouped into consecutive segments whose workspace fits
+ * opt->ws_budget (default: half the free device memory, at most 64 GiB); the
+ * segments run one after another inside the graph and share one workspace.
+ * The graph owns its device memory (hipMalloc at creation; see
+ * te_batch_graph_info) until te_batch_graph_destroy.  Returns NULL on failure
+ * with *rc (may be NULL) set to the error code (TE_ERR_WORKSPACE if a single
+ * problem does not fit the budget or the memory cannot be allocated). */
+te_batch_graph *te_batch_graph_create(const double *d_all, const double *e_all, const int64_t *off,
+                                      const int *il, const int *iu, double *W_all,
+                                      const int64_t *woff, double *Z_all, const int64_t *zoff,
+                                      int B, const te_opts *opt, const te_graph_cfg *cfg,
+                                      int *rc);
+
+/* Run the whole batch: one hipGraphLaunch on `stream`, which is synchronized
+ * before returning.  Call on the device the graph was built on.
+ * Returns 0, -1 for a NULL graph, TE_ERR_KERNEL if a chain's internal wait
+ * timed out (its results are then incomplete), or another TE_ERR_*. */
+int te_batch_graph_launch(te_batch_graph *g, hipStream_t stream);
+
+/* The graph's chain configuration, number of segments and device bytes it
+ * owns (any pointer may be NULL).  Returns 0, or -1 for a NULL graph. */
+int te_batch_graph_info(const te_batch_graph *g, te_graph_cfg *cfg, int *segments,
+                        uint64_t *device_bytes);
+
+/* Free the graph and its device memory (waits for the device). */
+void te_batch_graph_destroy(te_batch_graph *g);
+
+/* Autotuner of the graph path.  Times every candidate configuration
+ * (chain_threads 256 and 512, chains_per_cu 1, 2, 4, ... up to each variant's
+ * occupancy limit) on a sample of the batch (every (B / 512)-th problem, at
+ * least every problem when B < 1024): one warm-up launch and one timed launch
+ * of that sample's graph each.  The fastest goes into the process's autotune
+ * table under the batch's shape key (ceil log2 of the largest n, ceil log2 of
+ * the mean n), and, when the environment variable TE_TUNE_FILE names a file,
+ * is appended to it as a line "nbits mbits chain_threads chains_per_cu"; that
+ * file is read once, on first use of the table.  The sampled problems'
+ * results are written to W_all and Z_all.  best (may be NULL) receives the
+ * winner; tried and ms (may be NULL, cap entries) the candidates and their
+ * times in milliseconds, *ntried (may be NULL) how many were timed.
+ * Arguments 1-11 as for te_batch_graph_create. */
+int te_batch_autotune(const double *d_all, const double *e_all, const int64_t *off, const int *il,
+                      const int *iu, double *W_all, const int64_t *woff, double *Z_all,
+                      const int64_t *zoff, int B, const te_opts *opt, te_graph_cfg *best,
+                      te_graph_cfg *tried, double *ms, int cap, int *ntried);
+
 /* Eigenvalues only: lambda_il..lambda_iu of T by Sturm-count bisection, into
  * W[0..m-1] (device).  Counts are exact integers; W is the bracket midpoint
  * after the bracket [gl, gu] (Gershgorin, widened until count(gl) = 0 and

@@ -20,6 +20,8 @@ SYMBOLS = ("tridiag_eigvecs", "tridiag_eigvecs_given_w", "tridiag_eigvecs_worksp
            "tridiag_eigvecs_ex", "tridiag_eigvecs_batched", "tridiag_eigvals", "tridiag_clusters",
            "te_server_create", "te_server_submit", "te_server_poll", "te_server_wait",
            "te_server_times", "te_server_destroy",
+           "te_batch_graph_create", "te_batch_graph_launch", "te_batch_graph_info",
+           "te_batch_graph_destroy", "te_batch_autotune",
            "te_timing_enable", "te_timing_reset", "te_timing_read", "te_last_hip_error")
 PHASES = ("setup", "bisect", "clusters", "first_solves", "transpose", "chain_small",
           "chain_coop", "finalize")
@@ -37,6 +39,10 @@ class te_opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("cluster_rtol", ctypes.c_double),
                 ("coop_wgs", ctypes.c_int), ("_reserved1", ctypes.c_int),
                 ("ws_budget", ctypes.c_uint64)]
+
+
+class te_graph_cfg(ctypes.Structure):
+    _fields_ = [("chain_threads", ctypes.c_int), ("chains_per_cu", ctypes.c_int)]
 
 
 _lib = None
@@ -76,6 +82,16 @@ def lib():
         L.te_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_longlong), i]
         L.te_last_hip_error.restype = i
+        cfgp = ctypes.POINTER(te_graph_cfg)
+        batch = [_vp, _vp, i64p, ip, ip, _vp, i64p, _vp, i64p, i, ctypes.POINTER(te_opts)]
+        L.te_batch_graph_create.argtypes = batch + [cfgp, ip]
+        L.te_batch_graph_create.restype = _vp
+        L.te_batch_graph_launch.argtypes = [_vp, _vp]
+        L.te_batch_graph_info.argtypes = [_vp, cfgp, ip, ctypes.POINTER(ctypes.c_uint64)]
+        L.te_batch_graph_destroy.argtypes = [_vp]
+        L.te_batch_graph_destroy.restype = None
+        L.te_batch_autotune.argtypes = batch + [cfgp, cfgp, ctypes.POINTER(ctypes.c_double), i,
+                                                ip]
         _lib = L
     return _lib
 
@@ -239,75 +255,140 @@ def tridiag_eigvecs_ex(d, e, il=1, iu=None, W_given=None, ws=None, info=None, st
     return W[:m], Z[:m], info
 
 
-def tridiag_eigvecs_batched_raw(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff, stream=None,
-                                **opts):
-    """Batched call on device tensors already laid out as the C-ABI expects;
-    off/il/iu/woff/zoff are host numpy arrays (int64, int32, int32, int64, int64)."""
-    i64p = ctypes.POINTER(ctypes.c_int64)
-    ip = ctypes.POINTER(ctypes.c_int)
-    off = np.ascontiguousarray(off, dtype=np.int64)
-    il = np.ascontiguousarray(il, dtype=np.int32)
-    iu = np.ascontiguousarray(iu, dtype=np.int32)
-    woff = np.ascontiguousarray(woff, dtype=np.int64)
-    zoff = np.ascontiguousarray(zoff, dtype=np.int64)
-    o = _opts(**opts)
-    rc = lib().tridiag_eigvecs_batched(_vp(d_all.data_ptr()), _vp(e_all.data_ptr()),
-                                       off.ctypes.data_as(i64p), il.ctypes.data_as(ip),
-                                       iu.ctypes.data_as(ip), _vp(W_all.data_ptr()),
-                                       woff.ctypes.data_as(i64p), _vp(Z_all.data_ptr()),
-                                       zoff.ctypes.data_as(i64p), len(il), ctypes.byref(o),
-                                       _stream_ptr(stream))
-    _check("tridiag_eigvecs_batched", rc)
+class BatchLayout:
+    """Problems packed as the batched entry points expect: d_all, e_all on the
+    device; off, il, iu, woff, zoff on the host; W_all and Z_all device outputs."""
+
+    def __init__(self, problems, device="cuda"):
+        torch = _torch()
+        B = len(problems)
+        ns, ils, ius, ds, es = [], [], [], [], []
+        for p in problems:
+            d, e = p[0], p[1]
+            n = len(d)
+            il, iu = (p[2], p[3]) if len(p) >= 4 else (1, n)
+            ns.append(n)
+            ils.append(il)
+            ius.append(iu)
+            ds.append(_host_f64(d))
+            es.append(_host_f64(e))
+        self.B = B
+        self.ns = ns
+        self.off = np.zeros(B + 1, dtype=np.int64)
+        self.off[1:] = np.cumsum(ns)
+        self.ms = np.array([iu - il + 1 for il, iu in zip(ils, ius)], dtype=np.int64)
+        self.woff = np.zeros(B, dtype=np.int64)
+        self.woff[1:] = np.cumsum(self.ms)[:-1]
+        zsz = self.ms * np.array(ns, dtype=np.int64)
+        self.zoff = np.zeros(B, dtype=np.int64)
+        self.zoff[1:] = np.cumsum(zsz)[:-1]
+        self.d_all = _dev_f64(np.concatenate(ds), device)
+        e_cat = (np.concatenate([x for x in es if len(x)]) if any(len(x) for x in es)
+                 else np.zeros(1))
+        self.e_all = _dev_f64(e_cat, device)
+        self.W_all = torch.empty(int(self.ms.sum()), dtype=torch.float64, device=self.d_all.device)
+        self.Z_all = torch.empty(int(zsz.sum()), dtype=torch.float64, device=self.d_all.device)
+        self.il = np.asarray(ils, dtype=np.int32)
+        self.iu = np.asarray(ius, dtype=np.int32)
+
+    def args(self):
+        """The first ten C-ABI arguments of the batched entry points."""
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        ip = ctypes.POINTER(ctypes.c_int)
+        return (_vp(self.d_all.data_ptr()), _vp(self.e_all.data_ptr()),
+                self.off.ctypes.data_as(i64p), self.il.ctypes.data_as(ip),
+                self.iu.ctypes.data_as(ip), _vp(self.W_all.data_ptr()),
+                self.woff.ctypes.data_as(i64p), _vp(self.Z_all.data_ptr()),
+                self.zoff.ctypes.data_as(i64p), self.B)
+
+    def results(self):
+        """List of (W, Z) views per problem (Z row j = eigenvector of W[j])."""
+        out = []
+        for b in range(self.B):
+            m, n = int(self.ms[b]), self.ns[b]
+            W = self.W_all[self.woff[b]: self.woff[b] + m]
+            Z = self.Z_all[self.zoff[b]: self.zoff[b] + m * n].view(m, n)
+            out.append((W, Z))
+        return out
 
 
 def tridiag_eigvecs_batched(problems, stream=None, device="cuda", **opts):
     """problems: list of (d, e) or (d, e, il, iu) (numpy or tensors).
     Returns a list of (W, Z) per problem (Z row j = eigenvector of W[j])."""
-    torch = _torch()
-    B = len(problems)
-    ns, ils, ius = [], [], []
-    ds, es = [], []
-    for p in problems:
-        d, e = p[0], p[1]
-        n = len(d)
-        il, iu = (p[2], p[3]) if len(p) >= 4 else (1, n)
-        ns.append(n)
-        ils.append(il)
-        ius.append(iu)
-        ds.append(_host_f64(d))
-        es.append(_host_f64(e))
-    off = np.zeros(B + 1, dtype=np.int64)
-    off[1:] = np.cumsum(ns)
-    ms = np.array([iu - il + 1 for il, iu in zip(ils, ius)], dtype=np.int64)
-    woff = np.zeros(B, dtype=np.int64)
-    woff[1:] = np.cumsum(ms)[:-1]
-    zsz = ms * np.array(ns, dtype=np.int64)
-    zoff = np.zeros(B, dtype=np.int64)
-    zoff[1:] = np.cumsum(zsz)[:-1]
-    d_all = _dev_f64(np.concatenate(ds), device)
-    e_cat = np.concatenate([x for x in es if len(x)]) if any(len(x) for x in es) else np.zeros(1)
-    e_all = _dev_f64(e_cat, device)
-    W_all = torch.empty(int(ms.sum()), dtype=torch.float64, device=d_all.device)
-    Z_all = torch.empty(int(zsz.sum()), dtype=torch.float64, device=d_all.device)
-    il_a = np.asarray(ils, dtype=np.int32)
-    iu_a = np.asarray(ius, dtype=np.int32)
+    lay = problems if isinstance(problems, BatchLayout) else BatchLayout(problems, device)
     o = _opts(**opts)
-    i64p = ctypes.POINTER(ctypes.c_int64)
-    ip = ctypes.POINTER(ctypes.c_int)
-    rc = lib().tridiag_eigvecs_batched(_vp(d_all.data_ptr()), _vp(e_all.data_ptr()),
-                                       off.ctypes.data_as(i64p), il_a.ctypes.data_as(ip),
-                                       iu_a.ctypes.data_as(ip), _vp(W_all.data_ptr()),
-                                       woff.ctypes.data_as(i64p), _vp(Z_all.data_ptr()),
-                                       zoff.ctypes.data_as(i64p), B, ctypes.byref(o),
-                                       _stream_ptr(stream))
+    rc = lib().tridiag_eigvecs_batched(*lay.args(), ctypes.byref(o), _stream_ptr(stream))
     _check("tridiag_eigvecs_batched", rc)
-    out = []
-    for b in range(B):
-        m, n = int(ms[b]), ns[b]
-        W = W_all[woff[b]: woff[b] + m]
-        Z = Z_all[zoff[b]: zoff[b] + m * n].view(m, n)
-        out.append((W, Z))
-    return out
+    return lay.results()
+
+
+class BatchGraph:
+    """Graph-captured batched path (te_batch_graph_*).  The graph binds the
+    layout's device buffers: ``launch`` recomputes every problem from the
+    inputs d_all, e_all hold at that time into W_all, Z_all."""
+
+    def __init__(self, layout, chain_threads=None, chains_per_cu=None, **opts):
+        self.layout = layout
+        self._o = _opts(**opts)
+        cfg = None
+        if chain_threads is not None or chains_per_cu is not None:
+            cfg = te_graph_cfg(int(chain_threads or 256), int(chains_per_cu or 1))
+        rc = ctypes.c_int(0)
+        h = lib().te_batch_graph_create(*layout.args(), ctypes.byref(self._o),
+                                        ctypes.byref(cfg) if cfg is not None else None,
+                                        ctypes.byref(rc))
+        if not h:
+            raise TeError("te_batch_graph_create", rc.value, lib().te_last_hip_error())
+        self._h = ctypes.c_void_p(h)
+
+    def launch(self, stream=None):
+        _check("te_batch_graph_launch", lib().te_batch_graph_launch(self._h, _stream_ptr(stream)))
+        return self.layout.results()
+
+    def info(self):
+        """{'chain_threads', 'chains_per_cu', 'segments', 'device_bytes'}"""
+        c = te_graph_cfg()
+        seg = ctypes.c_int(0)
+        nb = ctypes.c_uint64(0)
+        _check("te_batch_graph_info",
+               lib().te_batch_graph_info(self._h, ctypes.byref(c), ctypes.byref(seg),
+                                         ctypes.byref(nb)))
+        return {"chain_threads": c.chain_threads, "chains_per_cu": c.chains_per_cu,
+                "segments": seg.value, "device_bytes": nb.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().te_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_autotune(layout, **opts):
+    """te_batch_autotune on a BatchLayout.  Returns (best, [(cfg, ms), ...])
+    with cfg = (chain_threads, chains_per_cu)."""
+    o = _opts(**opts)
+    cap = 32
+    best = te_graph_cfg()
+    tried = (te_graph_cfg * cap)()
+    ms = (ctypes.c_double * cap)()
+    nt = ctypes.c_int(0)
+    rc = lib().te_batch_autotune(*layout.args(), ctypes.byref(o), ctypes.byref(best), tried, ms,
+                                 cap, ctypes.byref(nt))
+    _check("te_batch_autotune", rc)
+    res = [((tried[k].chain_threads, tried[k].chains_per_cu), ms[k])
+           for k in range(min(nt.value, cap))]
+    return (best.chain_threads, best.chains_per_cu), res
 
 
 class Server:

@@ -658,6 +658,374 @@ int solve_batched(const std::vector<ProblemDesc> &pd, const Resolved &opt, hipSt
   return 0;
 }
 
+
+// Argument checks of the batched entry points (positions as in
+// tridiag_eigvecs_batched) and the problem descriptors.
+int batch_descs(const double *d_all, const double *e_all, const int64_t *off, const int *il,
+                const int *iu, double *W_all, const int64_t *woff, double *Z_all,
+                const int64_t *zoff, int B, const te_opts *opt, std::vector<ProblemDesc> &pd) {
+  if (!d_all) return -1;
+  if (!off) return -3;
+  if (!il) return -4;
+  if (!iu) return -5;
+  if (!W_all) return -6;
+  if (!woff) return -7;
+  if (!Z_all) return -8;
+  if (!zoff) return -9;
+  if (B < 1) return -10;
+  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0)) return -11;
+  pd.assign((size_t)B, ProblemDesc{});
+  bool any_e = false;
+  for (int b = 0; b < B; b++) {
+    const int64_t nb = off[b + 1] - off[b];
+    if (nb < 1 || nb > (1 << 30)) return -3;
+    if (il[b] < 1 || il[b] > nb) return -4;
+    if (iu[b] < il[b] || iu[b] > nb) return -5;
+    if (nb > 1) any_e = true;
+    pd[b].d = d_all + off[b];
+    pd[b].e = e_all ? e_all + (off[b] - b) : nullptr;
+    pd[b].n = (int)nb;
+    pd[b].il = il[b];
+    pd[b].iu = iu[b];
+    pd[b].W = W_all + woff[b];
+    pd[b].Z = Z_all + zoff[b];
+    pd[b].ldz = (int)nb;
+  }
+  if (any_e && !e_all) return -2;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Graph-captured batched path.  The batch is cut into segments whose
+// workspace fits the budget (consecutive problems, as in solve_batched); each
+// segment runs the whole method with every step on the device: the chain plan
+// comes from k_plan_* instead of a host round trip, and every chain (whatever
+// its size) runs in one workgroup of the persistent small-chain kernel.  All
+// segments are captured into one graph; its launch is one hipGraphLaunch.
+// Segments share one workspace region (they run one after another); their
+// descriptors, parameters and info flags live in per-segment regions written
+// once at creation.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct GraphSeg {
+  int nprob = 0;
+  Prob *dprobs = nullptr;
+  int64_t *dloff = nullptr;
+  int nmax = 0, mmax = 0;
+  int64_t mtotal = 0;
+  int *info = nullptr;   // contiguous info arrays of the segment's problems
+  size_t info_ints = 0;
+  ChainScratch scr{};
+  ChainItem *items = nullptr;
+  int item_cap = 0;
+  int *nitems = nullptr, *bins = nullptr;
+  int *flags = nullptr;  // abort, counter (in the segment's own region)
+};
+
+size_t seg_fixed_bytes(const std::vector<ProblemDesc> &pd, size_t b0, size_t b1) {
+  size_t b = fixed_bytes((int)(b1 - b0)) + align_up(sizeof(int) * 2);  // + abort flag, counter
+  for (size_t k = b0; k < b1; k++)
+    b += align_up(sizeof(Params)) + align_up(sizeof(int) * ((size_t)(pd[k].iu - pd[k].il + 1) + 1));
+  return b;
+}
+
+size_t seg_shared_bytes(const std::vector<ProblemDesc> &pd, size_t b0, size_t b1, int nslots) {
+  size_t b = 0;
+  int nmax = 0, mmax = 0;
+  size_t cap = 0;
+  for (size_t k = b0; k < b1; k++) {
+    const int m = pd[k].iu - pd[k].il + 1;
+    const ProbLayout L = prob_layout(pd[k].n, m);
+    b += L.total() - L.prm - L.info;
+    nmax = std::max(nmax, pd[k].n);
+    mmax = std::max(mmax, m);
+    cap += (size_t)(m / 2);
+  }
+  b += align_up(sizeof(double) * chain_scratch_doubles(nmax, mmax, 1) * (size_t)std::max(nslots, 1));
+  b += align_up(sizeof(ChainItem) * std::max<size_t>(cap, 1));
+  b += align_up(sizeof(int) * (2 * kPlanBins + 4));
+  return b;
+}
+
+// Cut [0, B) into consecutive segments of at most `budget` bytes each.
+bool plan_segments(const std::vector<ProblemDesc> &pd, int nslots, uint64_t budget,
+                   std::vector<std::pair<size_t, size_t>> &seg) {
+  seg.clear();
+  size_t b0 = 0;
+  while (b0 < pd.size()) {
+    size_t b1 = b0 + 1;
+    auto need = [&](size_t e) { return seg_fixed_bytes(pd, b0, e) + seg_shared_bytes(pd, b0, e, nslots); };
+    if (need(b1) > budget) return false;
+    while (b1 < pd.size() && need(b1 + 1) <= budget) b1++;
+    seg.push_back({b0, b1});
+    b0 = b1;
+  }
+  return true;
+}
+
+// Carve segment [b0, b1): fixed part from fx, problem arrays and chain state
+// from sh.  Uploads the descriptors and parameters (synchronous copies).
+int carve_segment(const std::vector<ProblemDesc> &pd, size_t b0, size_t b1, const Resolved &opt,
+                  int nslots, Carve &fx, Carve &sh, GraphSeg &G) {
+  const int nprob = (int)(b1 - b0);
+  G.nprob = nprob;
+  std::vector<Prob> hp((size_t)nprob);
+  std::vector<int64_t> loff((size_t)nprob + 1, 0);
+  std::vector<Params> hprm((size_t)nprob);
+  G.dprobs = fx.take<Prob>(sizeof(Prob) * nprob);
+  G.dloff = fx.take<int64_t>(sizeof(int64_t) * (nprob + 1));
+  // parameters first, then the info arrays back to back, so that one fill
+  // clears every info array and nothing else
+  for (int q = 0; q < nprob; q++) hp[q].prm = fx.take<Params>(sizeof(Params));
+  size_t cap = 0;
+  char *info0 = nullptr, *info1 = nullptr;
+  for (int q = 0; q < nprob; q++) {
+    const ProblemDesc &D = pd[b0 + q];
+    const int n = D.n, m = D.iu - D.il + 1;
+    const size_t nm = (size_t)n * m;
+    loff[q + 1] = loff[q] + m;
+    G.nmax = std::max(G.nmax, n);
+    G.mmax = std::max(G.mmax, m);
+    cap += (size_t)(m / 2);
+    Prob &P = hp[q];
+    Params *prm = P.prm;
+    std::memset(&P, 0, sizeof(P));
+    P.d = D.d; P.e = D.e; P.n = n; P.m = m; P.ldz = D.ldz; P.kbase = D.il; P.W = D.W; P.Z = D.Z;
+    P.prm = prm;
+    P.info = fx.take<int>(sizeof(int) * ((size_t)m + 1));
+    if (!info0) info0 = reinterpret_cast<char *>(P.info);
+    info1 = reinterpret_cast<char *>(P.info) + align_up(sizeof(int) * ((size_t)m + 1));
+    P.e2 = sh.take<double>(sizeof(double) * std::max(n - 1, 1));
+    P.nrm = sh.take<double>(sizeof(double) * m);
+    P.pos = sh.take<int>(sizeof(int) * m);
+    P.cl_start = sh.take<int>(sizeof(int) * m);
+    P.cl_size = sh.take<int>(sizeof(int) * m);
+    P.ncl = sh.take<int>(sizeof(int));
+    P.V = sh.take<double>(sizeof(double) * nm);
+    P.Ll = sh.take<double>(sizeof(double) * nm);
+    P.Lu1i = sh.take<double>(sizeof(double) * nm);
+    P.Lu2 = sh.take<double>(sizeof(double) * nm);
+    P.Lu3 = sh.take<double>(sizeof(double) * nm);
+    P.Lsw = sh.take<unsigned char>(nm);
+    P.Lrec = sh.take<double>(4 * sizeof(double) * nm);
+    P.Lswb = sh.take<unsigned char>(nm);
+    P.ldy = (int)even((size_t)n);
+    P.ldm = (int)even((size_t)m);
+    P.Y = sh.take<double>(sizeof(double) * (size_t)P.ldy * m);
+    P.Yr = sh.take<double>(sizeof(double) * (size_t)n * P.ldm);
+    P.T = sh.take<double>(sizeof(double) * (size_t)P.ldm * P.ldm);
+    P.Tr = sh.take<double>(sizeof(double) * (size_t)P.ldm * P.ldm);
+    std::memset(&hprm[q], 0, sizeof(Params));
+    hprm[q].rtol = opt.rtol;
+  }
+  G.mtotal = loff[nprob];
+  G.info = reinterpret_cast<int *>(info0);
+  G.info_ints = (size_t)(info1 - info0) / sizeof(int);
+  G.scr.stride = chain_scratch_doubles(G.nmax, G.mmax, 1);
+  G.scr.base = sh.take<double>(sizeof(double) * G.scr.stride * (size_t)std::max(nslots, 1));
+  G.item_cap = (int)std::max<size_t>(cap, 1);
+  G.items = sh.take<ChainItem>(sizeof(ChainItem) * (size_t)G.item_cap);
+  int *ints = sh.take<int>(sizeof(int) * (2 * kPlanBins + 4));
+  G.bins = ints;
+  G.nitems = ints + 2 * kPlanBins;
+  // the flags stay readable after later segments have reused the shared region
+  G.flags = fx.take<int>(sizeof(int) * 2);
+  if (fx.off > fx.cap || sh.off > sh.cap) return TE_ERR_WORKSPACE;
+  TE_CHECK(hipMemcpy(G.dprobs, hp.data(), sizeof(Prob) * nprob, hipMemcpyHostToDevice));
+  TE_CHECK(hipMemcpy(G.dloff, loff.data(), sizeof(int64_t) * (nprob + 1), hipMemcpyHostToDevice));
+  for (int q = 0; q < nprob; q++)
+    TE_CHECK(hipMemcpy(hp[q].prm, &hprm[q], sizeof(Params), hipMemcpyHostToDevice));
+  return 0;
+}
+
+// Every step of one segment, device-only (capturable).
+int enqueue_segment(const GraphSeg &G, const Resolved &opt, int nt, int nwg, hipStream_t s) {
+  TE_CHECK(launch_fill_i32(G.info, G.info_ints, 0, s));
+  TE_CHECK(launch_setup(G.dprobs, G.nprob, s));
+  TE_CHECK(launch_bisect(G.dprobs, G.nprob, G.dloff, G.mtotal, s));
+  TE_CHECK(launch_cluster(G.dprobs, G.nprob, s));
+  TE_CHECK(launch_invit(G.dprobs, G.nprob, G.dloff, G.mtotal, opt.iters, opt.seed, s));
+  TE_CHECK(launch_transpose(G.dprobs, G.nprob, G.nmax, G.mmax, s));
+  TE_CHECK(launch_plan(G.dprobs, G.nprob, G.bins, G.items, G.nitems, s));
+  TE_CHECK(launch_fill_i32(G.flags, 2, 0, s));
+  TE_CHECK(launch_chain_small_dev(G.dprobs, G.items, G.item_cap, G.nitems, G.flags + 1, G.flags,
+                                  G.scr, nwg, nt, opt.iters, s));
+  TE_CHECK(launch_finalize(G.dprobs, G.nprob, G.dloff, G.mtotal, s));
+  return 0;
+}
+
+// ---- autotune table: (ceil log2 max n, ceil log2 mean n) -> configuration ----
+int ceil_log2(double x) {
+  int e = 0;
+  while ((double)(1LL << e) < x && e < 62) e++;
+  return e;
+}
+
+std::pair<int, int> tune_key(const std::vector<ProblemDesc> &pd) {
+  double nmax = 1, nsum = 0;
+  for (const auto &D : pd) {
+    nmax = std::max(nmax, (double)D.n);
+    nsum += D.n;
+  }
+  return {ceil_log2(nmax), ceil_log2(nsum / (double)std::max<size_t>(pd.size(), 1))};
+}
+
+std::mutex g_tune_mu;
+bool g_tune_loaded = false;
+std::vector<std::pair<std::pair<int, int>, te_graph_cfg>> g_tune;
+
+const char *tune_file() {
+  const char *f = getenv("TE_TUNE_FILE");
+  return (f && f[0]) ? f : nullptr;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *f = tune_file();
+  if (!f) return;
+  FILE *fp = fopen(f, "r");
+  if (!fp) return;
+  char line[256];
+  while (fgets(line, sizeof line, fp)) {
+    int nb, mb, nt, per;
+    if (line[0] == '#') continue;
+    if (sscanf(line, "%d %d %d %d", &nb, &mb, &nt, &per) == 4 &&
+        (nt == 256 || nt == 512) && per >= 1) {
+      te_graph_cfg c{nt, per};
+      bool found = false;
+      for (auto &e : g_tune)
+        if (e.first == std::make_pair(nb, mb)) { e.second = c; found = true; }
+      if (!found) g_tune.push_back({{nb, mb}, c});
+    }
+  }
+  fclose(fp);
+}
+
+bool tune_lookup(std::pair<int, int> key, te_graph_cfg &out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  for (const auto &e : g_tune)
+    if (e.first == key) { out = e.second; return true; }
+  return false;
+}
+
+void tune_store(std::pair<int, int> key, const te_graph_cfg &c, double ms) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  bool found = false;
+  for (auto &e : g_tune)
+    if (e.first == key) { e.second = c; found = true; }
+  if (!found) g_tune.push_back({key, c});
+  const char *f = tune_file();
+  if (!f) return;
+  if (FILE *fp = fopen(f, "a")) {
+    fprintf(fp, "%d %d %d %d  # %.3f ms on the tuning sample\n", key.first, key.second,
+            c.chain_threads, c.chains_per_cu, ms);
+    fclose(fp);
+  }
+}
+
+// Resident chain workgroups per CU for nt threads (0 if the variant does not fit).
+int per_cu_max(int device, int nt) {
+  const int ncu = device_cus(device);
+  if (ncu <= 0) return 0;
+  return small_max_wgs(device, nt) / ncu;
+}
+
+bool cfg_valid(int device, const te_graph_cfg &c) {
+  if (c.chain_threads != 256 && c.chain_threads != 512) return false;
+  return c.chains_per_cu >= 1 && c.chains_per_cu <= per_cu_max(device, c.chain_threads);
+}
+
+}  // namespace
+
+}  // namespace te
+
+struct te_batch_graph {
+  int device = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void *mem = nullptr;
+  size_t bytes = 0;
+  int nseg = 0;
+  std::vector<int *> abort_flags;  // one per segment, cleared by the graph itself
+  te_graph_cfg cfg{};
+  ~te_batch_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (mem) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(mem);
+    }
+    (void)hipGetLastError();
+  }
+};
+
+namespace te {
+namespace {
+
+// Builds and instantiates the graph of the whole batch with configuration c.
+int build_graph(const std::vector<ProblemDesc> &pd, const Resolved &opt, const te_graph_cfg &c,
+                te_batch_graph &g) {
+  const DeviceLimits lim = limits();
+  if (lim.device < 0) return TE_ERR_NO_DEVICE;
+  g.device = lim.device;
+  g.cfg = c;
+  const int nwg = device_cus(lim.device) * c.chains_per_cu;
+  const uint64_t budget = opt.ws_budget ? opt.ws_budget : default_budget();
+  std::vector<std::pair<size_t, size_t>> seg;
+  if (!plan_segments(pd, nwg, budget, seg)) return TE_ERR_WORKSPACE;
+  size_t fixed = 0, shared = 0;
+  for (auto &q : seg) {
+    fixed += seg_fixed_bytes(pd, q.first, q.second);
+    shared = std::max(shared, seg_shared_bytes(pd, q.first, q.second, nwg));
+  }
+  g.bytes = fixed + shared;
+  if (hipMalloc(&g.mem, g.bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    g.mem = nullptr;
+    return TE_ERR_WORKSPACE;
+  }
+  char *base = static_cast<char *>(g.mem);
+  Carve fx{base, 0, fixed};
+  std::vector<GraphSeg> G(seg.size());
+  for (size_t k = 0; k < seg.size(); k++) {
+    Carve sh{base + fixed, 0, shared};
+    const int rc = carve_segment(pd, seg[k].first, seg[k].second, opt, nwg, fx, sh, G[k]);
+    if (rc) return rc;
+  }
+  g.nseg = (int)seg.size();
+  for (const auto &q : G) g.abort_flags.push_back(q.flags);
+  hipStream_t cs = nullptr;
+  TE_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  int rc = 0;
+  if (e == hipSuccess) {
+    for (size_t k = 0; k < G.size() && rc == 0; k++)
+      rc = enqueue_segment(G[k], opt, c.chain_threads, nwg, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (rc == 0 && e2 != hipSuccess) rc = hip_fail(e2);
+    g.graph = graph;
+    if (rc == 0) {
+      const hipError_t e3 = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+      if (e3 != hipSuccess) rc = hip_fail(e3);
+    }
+  } else {
+    rc = hip_fail(e);
+  }
+  (void)hipStreamDestroy(cs);
+  return rc;
+}
+
+te_graph_cfg default_cfg(int device) {
+  te_graph_cfg c{256, std::max(per_cu_max(device, 256), 1)};
+  return c;
+}
+
+}  // namespace
 }  // namespace te
 
 using namespace te;
@@ -822,35 +1190,143 @@ int tridiag_eigvecs_batched(const double *d_all, const double *e_all, const int6
                             const int *il, const int *iu, double *W_all, const int64_t *woff,
                             double *Z_all, const int64_t *zoff, int B, const te_opts *opt,
                             hipStream_t stream) {
-  if (!d_all) return -1;
-  if (!off) return -3;
-  if (!il) return -4;
-  if (!iu) return -5;
-  if (!W_all) return -6;
-  if (!woff) return -7;
-  if (!Z_all) return -8;
-  if (!zoff) return -9;
-  if (B < 1) return -10;
-  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0)) return -11;
-  std::vector<ProblemDesc> pd(B);
-  bool any_e = false;
-  for (int b = 0; b < B; b++) {
-    const int64_t nb = off[b + 1] - off[b];
-    if (nb < 1 || nb > (1 << 30)) return -3;
-    if (il[b] < 1 || il[b] > nb) return -4;
-    if (iu[b] < il[b] || iu[b] > nb) return -5;
-    if (nb > 1) any_e = true;
-    pd[b].d = d_all + off[b];
-    pd[b].e = e_all ? e_all + (off[b] - b) : nullptr;
-    pd[b].n = (int)nb;
-    pd[b].il = il[b];
-    pd[b].iu = iu[b];
-    pd[b].W = W_all + woff[b];
-    pd[b].Z = Z_all + zoff[b];
-    pd[b].ldz = (int)nb;
-  }
-  if (any_e && !e_all) return -2;
+  std::vector<ProblemDesc> pd;
+  const int rc = te::batch_descs(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff, B, opt, pd);
+  if (rc) return rc;
   return solve_batched(pd, resolve(opt), stream);
+}
+
+te_batch_graph *te_batch_graph_create(const double *d_all, const double *e_all, const int64_t *off,
+                                      const int *il, const int *iu, double *W_all,
+                                      const int64_t *woff, double *Z_all, const int64_t *zoff,
+                                      int B, const te_opts *opt, const te_graph_cfg *cfg,
+                                      int *rc) {
+  int r = 0;
+  te_batch_graph *g = nullptr;
+  try {
+    std::vector<te::ProblemDesc> pd;
+    r = te::batch_descs(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff, B, opt, pd);
+    if (r == 0) {
+      const te::DeviceLimits lim = te::limits();
+      if (lim.device < 0 || lim.small <= 0) {
+        r = TE_ERR_NO_DEVICE;
+      } else {
+        te_graph_cfg c = te::default_cfg(lim.device);
+        te_graph_cfg t;
+        if (cfg) {
+          if (!te::cfg_valid(lim.device, *cfg)) r = -12;
+          else c = *cfg;
+        } else if (te::tune_lookup(te::tune_key(pd), t) && te::cfg_valid(lim.device, t)) {
+          c = t;
+        }
+        if (r == 0) {
+          g = new te_batch_graph();
+          r = te::build_graph(pd, te::resolve(opt), c, *g);
+          if (r) {
+            delete g;
+            g = nullptr;
+          }
+        }
+      }
+    }
+  } catch (const std::bad_alloc &) {
+    delete g;
+    g = nullptr;
+    r = TE_ERR_WORKSPACE;
+  }
+  if (rc) *rc = r;
+  return g;
+}
+
+int te_batch_graph_launch(te_batch_graph *g, hipStream_t stream) {
+  if (!g || !g->exec) return -1;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != g->device) return TE_ERR_NO_DEVICE;
+  te::SharedHold hold;
+  hipError_t e = hipGraphLaunch(g->exec, stream);
+  if (e != hipSuccess) return te::hip_fail(e);
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return te::hip_fail(e);
+  for (int *f : g->abort_flags) {  // a chain wait that timed out fails the call
+    int a = 0;
+    e = hipMemcpy(&a, f, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return te::hip_fail(e);
+    if (a) return TE_ERR_KERNEL;
+  }
+  return 0;
+}
+
+int te_batch_graph_info(const te_batch_graph *g, te_graph_cfg *cfg, int *segments,
+                        uint64_t *device_bytes) {
+  if (!g) return -1;
+  if (cfg) *cfg = g->cfg;
+  if (segments) *segments = g->nseg;
+  if (device_bytes) *device_bytes = g->bytes;
+  return 0;
+}
+
+void te_batch_graph_destroy(te_batch_graph *g) { delete g; }
+
+int te_batch_autotune(const double *d_all, const double *e_all, const int64_t *off, const int *il,
+                      const int *iu, double *W_all, const int64_t *woff, double *Z_all,
+                      const int64_t *zoff, int B, const te_opts *opt, te_graph_cfg *best,
+                      te_graph_cfg *tried, double *ms, int cap, int *ntried) {
+  std::vector<te::ProblemDesc> pd;
+  int r = te::batch_descs(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff, B, opt, pd);
+  if (r) return r;
+  const te::DeviceLimits lim = te::limits();
+  if (lim.device < 0 || lim.small <= 0) return TE_ERR_NO_DEVICE;
+  // Sample: every stride-th problem, at most about 512 problems.
+  const size_t stride = std::max<size_t>(1, pd.size() / 512);
+  std::vector<te::ProblemDesc> sample;
+  for (size_t b = 0; b < pd.size(); b += stride) sample.push_back(pd[b]);
+  std::vector<te_graph_cfg> cand;
+  for (int nt : {256, 512}) {
+    const int pmax = te::per_cu_max(lim.device, nt);
+    for (int per = 1; per <= pmax; per *= 2) cand.push_back(te_graph_cfg{nt, per});
+    if (pmax >= 1 && (pmax & (pmax - 1)) != 0) cand.push_back(te_graph_cfg{nt, pmax});
+  }
+  if (cand.empty()) return TE_ERR_NO_DEVICE;
+  const te::Resolved o = te::resolve(opt);
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return TE_ERR_HIP;
+  hipEvent_t a = nullptr, z = nullptr;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&z);
+  double best_ms = 1e300;
+  te_graph_cfg bc = cand[0];
+  int k = 0;
+  for (const auto &c : cand) {
+    te_batch_graph g;
+    r = te::build_graph(sample, o, c, g);
+    if (r) break;
+    double t = 1e300;
+    for (int rep = 0; rep < 2 && r == 0; rep++) {  // the first launch warms up
+      te::SharedHold hold;
+      (void)hipEventRecord(a, s);
+      hipError_t e = hipGraphLaunch(g.exec, s);
+      (void)hipEventRecord(z, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) { r = te::hip_fail(e); break; }
+      float f = 0.f;
+      if (rep > 0 && hipEventElapsedTime(&f, a, z) == hipSuccess) t = f;
+    }
+    if (r) break;
+    if (k < cap) {
+      if (tried) tried[k] = c;
+      if (ms) ms[k] = t;
+    }
+    k++;
+    if (t < best_ms) { best_ms = t; bc = c; }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(z);
+  (void)hipStreamDestroy(s);
+  if (ntried) *ntried = k;
+  if (r) return r;
+  te::tune_store(te::tune_key(pd), bc, best_ms);
+  if (best) *best = bc;
+  return 0;
 }
 
 }  // extern "C"

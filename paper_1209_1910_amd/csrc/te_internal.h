@@ -101,10 +101,23 @@ hipError_t launch_chain_small(const Prob *probs, const ChainItem *items, int nit
 hipError_t launch_chain_coop(const Prob *probs, const ChainItem *items, const Group *groups,
                              const int *wg_group, unsigned *bars, int *abort_flag, int *started,
                              ChainScratch scr, int nwg, int iters, hipStream_t s);
+// Graph-capturable variant: the item count is read from nitems_dev (device)
+// when it is not null; nitems_cap bounds it otherwise.  nt: threads per
+// workgroup, 256 or 512 (identical results).
+hipError_t launch_chain_small_dev(const Prob *probs, const ChainItem *items, int nitems_cap,
+                                  const int *nitems_dev, int *counter, int *abort_flag,
+                                  ChainScratch scr, int nwg, int nt, int iters, hipStream_t s);
+// Device-side chain plan of nprob problems whose cluster tables are on the
+// device: items (capacity: the problems' sum of m / 2) ordered by decreasing
+// cost, their count in *nitems.  bins: 2 * kPlanBins ints of scratch.
+constexpr int kPlanBins = 64;
+hipError_t launch_plan(const Prob *probs, int nprob, int *bins, ChainItem *items, int *nitems,
+                       hipStream_t s);
 hipError_t launch_finalize(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
                            hipStream_t s);
 hipError_t launch_fill_i32(int *p, size_t n, int v, hipStream_t s);
 int coop_max_wgs(int device);
-int small_max_wgs(int device);
+int small_max_wgs(int device, int nt = 0);
+int device_cus(int device);
 
 }  // namespace te

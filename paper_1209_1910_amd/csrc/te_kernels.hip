@@ -270,6 +270,71 @@ hipError_t launch_cluster(const Prob *probs, int nprob, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Device-side chain plan (no host round trip, so the whole path can be
+// captured in a graph): every cluster of two or more members becomes a chain
+// item; items are ordered by decreasing cost size^2 n, in power-of-two cost
+// bins (bin 0 holds the most expensive), so that a persistent chain kernel
+// taking items from a counter starts the long chains first.  The order inside
+// a bin depends on atomic timing; every chain computes the same bits wherever
+// and whenever it runs.  bins: kPlanBins counts, then kPlanBins cursors.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int plan_bin(int size, int n) {
+  const double cost = (double)size * (double)size * (double)n;
+  const int e = ilogb(cost);  // >= 2 for size >= 2
+  return e >= kPlanBins - 1 ? 0 : kPlanBins - 1 - e;
+}
+
+__global__ void __launch_bounds__(256) k_plan_count(const Prob *__restrict__ probs, int *bins) {
+  const Prob &P = probs[blockIdx.x];
+  __shared__ int h[kPlanBins];
+  for (int i = threadIdx.x; i < kPlanBins; i += 256) h[i] = 0;
+  __syncthreads();
+  const int ncl = *P.ncl;
+  for (int c = threadIdx.x; c < ncl; c += 256) {
+    const int sz = P.cl_size[c];
+    if (sz >= 2) atomicAdd(&h[plan_bin(sz, P.n)], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kPlanBins; i += 256)
+    if (h[i]) atomicAdd(&bins[i], h[i]);
+}
+
+__global__ void k_plan_scan(int *bins, int *nitems) {
+  if (threadIdx.x != 0) return;
+  int acc = 0;
+  for (int i = 0; i < kPlanBins; i++) {
+    const int c = bins[i];
+    bins[kPlanBins + i] = acc;
+    acc += c;
+  }
+  *nitems = acc;
+}
+
+__global__ void __launch_bounds__(256) k_plan_scatter(const Prob *__restrict__ probs, int *bins,
+                                                      ChainItem *__restrict__ items) {
+  const Prob &P = probs[blockIdx.x];
+  const int ncl = *P.ncl;
+  for (int c = threadIdx.x; c < ncl; c += 256) {
+    const int sz = P.cl_size[c];
+    if (sz < 2) continue;
+    const int at = atomicAdd(&bins[kPlanBins + plan_bin(sz, P.n)], 1);
+    items[at] = ChainItem{(int)blockIdx.x, P.cl_start[c], sz, 0};
+  }
+}
+
+hipError_t launch_plan(const Prob *probs, int nprob, int *bins, ChainItem *items, int *nitems,
+                       hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  hipError_t e = launch_fill_i32(bins, 2 * kPlanBins, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_plan_count, dim3(nprob), dim3(256), 0, s, probs, bins);
+  hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, s, bins, nitems);
+  hipLaunchKernelGGL(k_plan_scatter, dim3(nprob), dim3(256), 0, s, probs, bins, items);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // a4-a6: start vectors, partial-pivoting LU of T - lambda_j I and the solves
 // of Eq. (1); one lane per eigenvalue, interleaved storage.
 //
@@ -1443,18 +1508,23 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
 constexpr int kSmallThreads = 256;
 constexpr int kCoopThreads = 512;
 
-// Small clusters: one workgroup per cluster, items taken from a work counter.
-__global__ void __launch_bounds__(kSmallThreads) k_chain_small(const Prob *__restrict__ probs,
-                                                               const ChainItem *__restrict__ items,
-                                                               int nitems, int *counter,
-                                                               int *abort_flag,
-                                                               ChainScratch scr, int iters) {
+// Small clusters: one workgroup of NT threads per cluster, items taken from a
+// work counter.  The item count is nitems, or *nitems_dev when that is not
+// null (a plan written on the device by k_plan_scatter).  Every chain sum has
+// one order for any NT (see grp_sumsq), so the variants give identical bits.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_chain_small(const Prob *__restrict__ probs,
+                                                    const ChainItem *__restrict__ items,
+                                                    int nitems, const int *nitems_dev,
+                                                    int *counter, int *abort_flag,
+                                                    ChainScratch scr, int iters) {
   __shared__ int s_item;
   Ctx cx;
   cx.rank = 0; cx.size = 1; cx.cnt = nullptr; cx.flag = nullptr; cx.gen = 0; cx.sgen = 0;
   cx.abort_flag = abort_flag;
   cx.wave = threadIdx.x / kWave; cx.lane = threadIdx.x % kWave;
-  cx.gw = cx.wave; cx.nw = kSmallThreads / kWave;
+  cx.gw = cx.wave; cx.nw = NT / kWave;
+  if (nitems_dev) nitems = *nitems_dev;
   double *base = as_global(scr.base + (size_t)blockIdx.x * scr.stride);
   for (;;) {
     // after a failed run (abort flag set) no further items are taken
@@ -1469,7 +1539,14 @@ __global__ void __launch_bounds__(kSmallThreads) k_chain_small(const Prob *__res
     const ChainItem it = items[idx];
     const Prob &P = probs[it.prob];
     const Scr S = make_scr(base, P.n, P.m, it.start & 1);
-    run_chain<kSmallThreads>(cx, P, it, S, iters);
+    run_chain<NT>(cx, P, it, S, iters);
+  }
+}
+
+static const void *small_kernel(int nt) {
+  switch (nt) {
+    case 512: return (const void *)k_chain_small<512>;
+    default: return (const void *)k_chain_small<kSmallThreads>;
   }
 }
 
@@ -1477,8 +1554,24 @@ hipError_t launch_chain_small(const Prob *probs, const ChainItem *items, int nit
                               int *abort_flag, ChainScratch scr, int nwg, int iters,
                               hipStream_t s) {
   if (nitems <= 0 || nwg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_chain_small, dim3(nwg), dim3(kSmallThreads), 0, s, probs, items, nitems,
-                     counter, abort_flag, scr, iters);
+  return launch_chain_small_dev(probs, items, nitems, nullptr, counter, abort_flag, scr, nwg,
+                                kSmallThreads, iters, s);
+}
+
+hipError_t launch_chain_small_dev(const Prob *probs, const ChainItem *items, int nitems_cap,
+                                  const int *nitems_dev, int *counter, int *abort_flag,
+                                  ChainScratch scr, int nwg, int nt, int iters, hipStream_t s) {
+  if (nwg <= 0) return hipSuccess;
+  if (nt != kSmallThreads && nt != 512) return hipErrorInvalidValue;
+  switch (nt) {
+    case 512:
+      hipLaunchKernelGGL(k_chain_small<512>, dim3(nwg), dim3(512), 0, s, probs, items, nitems_cap,
+                         nitems_dev, counter, abort_flag, scr, iters);
+      break;
+    default:
+      hipLaunchKernelGGL(k_chain_small<kSmallThreads>, dim3(nwg), dim3(kSmallThreads), 0, s,
+                         probs, items, nitems_cap, nitems_dev, counter, abort_flag, scr, iters);
+  }
   return hipGetLastError();
 }
 
@@ -1566,14 +1659,21 @@ int coop_max_wgs(int device) {
   return per >= 1 ? ncu : 0;
 }
 
-int small_max_wgs(int device) {
+int small_max_wgs(int device, int nt) {
   int ncu = 0, per = 0;
+  if (nt <= 0) nt = kSmallThreads;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain_small,
-                                                   kSmallThreads, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, small_kernel(nt), nt, 0) != hipSuccess)
     return 0;
   return ncu * per;
+}
+
+int device_cus(int device) {
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 0;
+  return ncu;
 }
 
 // ---------------------------------------------------------------------------

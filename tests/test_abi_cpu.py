@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "tridiag_eigvecs.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:int|size_t|void|te_server)\s+\**\s*(\w+)\s*\(", src,
+    names = re.findall(r"^\s*(?:int|size_t|void|te_server|te_batch_graph)\s+\**\s*(\w+)\s*\(", src,
                        flags=re.M)
     return sorted(set(names))
 
@@ -94,3 +94,42 @@ def test_server_argument_errors():
     o.coop_wgs = -2
     assert not L.te_server_create(0, 1, ctypes.byref(o))
     L.te_server_destroy(NULL)
+
+
+def test_batch_graph_and_autotune_argument_errors():
+    """The graph path checks the batched arguments on the host, in the
+    positions of tridiag_eigvecs_batched, before any HIP call; a forced chain
+    configuration is checked next (argument 12)."""
+    import numpy as np
+    L = binding.lib()
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    off = np.array([0, 10, 16], dtype=np.int64)
+    il = np.array([1, 1], dtype=np.int32)
+    iu = np.array([10, 6], dtype=np.int32)
+    woff = np.array([0, 10], dtype=np.int64)
+    zoff = np.array([0, 100], dtype=np.int64)
+    A = (off.ctypes.data_as(i64p), il.ctypes.data_as(ip), iu.ctypes.data_as(ip))
+    W = woff.ctypes.data_as(i64p)
+    Zo = zoff.ctypes.data_as(i64p)
+    rc = ctypes.c_int(0)
+    g = L.te_batch_graph_create(NULL, P, *A, P, W, P, Zo, 2, None, None, ctypes.byref(rc))
+    assert not g and rc.value == -1
+    g = L.te_batch_graph_create(P, P, *A, P, W, P, Zo, 0, None, None, ctypes.byref(rc))
+    assert not g and rc.value == -10
+    bad_iu = np.array([11, 6], dtype=np.int32)
+    g = L.te_batch_graph_create(P, P, off.ctypes.data_as(i64p), il.ctypes.data_as(ip),
+                                bad_iu.ctypes.data_as(ip), P, W, P, Zo, 2, None, None,
+                                ctypes.byref(rc))
+    assert not g and rc.value == -5
+    o = binding.te_opts()
+    o.iters = -1
+    g = L.te_batch_graph_create(P, P, *A, P, W, P, Zo, 2, ctypes.byref(o), None, ctypes.byref(rc))
+    assert not g and rc.value == -11
+    assert L.te_batch_autotune(P, P, *A, NULL, W, P, Zo, 2, None, None, None, None, 0,
+                               None) == -6
+    assert L.te_batch_autotune(P, P, *A, P, W, P, None, 2, None, None, None, None, 0,
+                               None) == -9
+    assert L.te_batch_graph_launch(NULL, NULL) == -1
+    assert L.te_batch_graph_info(NULL, None, None, None) == -1
+    L.te_batch_graph_destroy(NULL)
