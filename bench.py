@@ -211,6 +211,90 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x, dtype=np.float64), q)) if len(x) else None
 
 
+PAPER_RATIOS = {  # t(DSTEIN, MGS) / t(DSTEIN-cWY) from Tables 3-8, computers 1 and 2
+    "type1": {1050: (0.94, 0.91), 2100: (1.10, 1.02), 4200: (2.22, 1.87)},
+    "type2": {1050: (3.85, 2.67), 2100: (21.93, 4.69), 4200: (10.45, 2.75)},
+    "type3": {1050: (3.66, 2.54), 2100: (4.62, 3.27), 4200: (6.71, 3.72)},
+}
+
+
+def _gpu_accuracy(d, e, W, Z):
+    """max ||T z - w z||_2 / ||T||_1 and max |Z Z^T - I| on the device (rows of Z
+    are the vectors)."""
+    import torch
+    n = d.numel()
+    TZ = Z * d[None, :]
+    if n > 1:
+        TZ[:, :-1] += Z[:, 1:] * e[None, :]
+        TZ[:, 1:] += Z[:, :-1] * e[None, :]
+    r = torch.linalg.vector_norm(TZ - Z * W[:, None], dim=1).max()
+    a = d.abs().clone()
+    if n > 1:
+        a[:-1] += e.abs()
+        a[1:] += e.abs()
+    G = Z @ Z.T
+    G.diagonal().sub_(1.0)
+    return float(r / a.max()), float(G.abs().max())
+
+
+def orth_bench(sizes) -> int:
+    """The paper's comparison on one MI355X: eigenvectors of its Type 1
+    (entries uniform in [0, 1)), Type 2 (tridiag(1, 1, 1)) and Type 3 (glued
+    Wilkinson W21+, delta = 1e-4) matrices at its sizes n = 1050 i, all
+    eigenvectors from given eigenvalues (bisection untimed, as in the paper),
+    with modified Gram-Schmidt (Alg. 1, DSTEIN) and with compact WY (Alg. 4,
+    DSTEIN-cWY) re-orthogonalization; one warm-up call and one timed call each."""
+    import torch
+
+    from paper_1209_1910_amd import binding, inputs
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for n in sizes:
+        for kind in ("type1", "type2", "type3"):
+            if kind == "type1":
+                d_np, e_np = inputs.type1_tridiag(n, 0)
+            elif kind == "type2":
+                d_np, e_np = inputs.type2_tridiag(n)
+            else:
+                d_np, e_np = inputs.glued_wilkinson(n // 21, 1e-4)
+            d = torch.from_numpy(d_np).to(dev)
+            e = torch.from_numpy(e_np).to(dev)
+            W = binding.tridiag_eigvals(d, e)
+            torch.cuda.synchronize()
+            row = {"type": kind, "n": int(d.numel())}
+            for orth in ("cwy", "mgs"):
+                binding.tridiag_eigvecs_ex(d, e, W_given=W, orth=orth)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, Z, _ = binding.tridiag_eigvecs_ex(d, e, W_given=W, orth=orth)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                res, orn = _gpu_accuracy(d, e, W, Z)
+                row[orth] = {"s": dt, "residual": res, "orthogonality": orn}
+                del Z
+                print(f"[bench] {kind} n={n} {orth}: {dt:.3f} s, residual {res:.2e}, "
+                      f"orthogonality {orn:.2e}", file=sys.stderr, flush=True)
+            row["mgs_over_cwy"] = row["mgs"]["s"] / row["cwy"]["s"]
+            pr = PAPER_RATIOS.get(kind, {}).get(n)
+            row["paper_ratio_c1_c2"] = list(pr) if pr else None
+            rows.append(row)
+    out = {
+        "metric": "time ratio t(MGS) / t(compact WY), all eigenvectors from given eigenvalues",
+        "value": max(r["mgs_over_cwy"] for r in rows),
+        "unit": "x",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "the paper's Type 1/2/3 matrices at n = " +
+                               ", ".join(str(n) for n in sizes) + ", all eigenvectors"},
+        "rows": rows,
+        "paper_context": "t/t_cwy from Tables 3-8 on 32-core Opteron (C1) and 8-core Xeon (C2)",
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def serving_bench(count: int, qps: float, budget_gib: float, lanes: int) -> int:
     """Serving workload: a Poisson request trace (seed 2) replayed in real
     time into the serving engine, then all at once (saturation), against the
@@ -343,7 +427,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (profiler counter calibration)")
-    ap.add_argument("--workload", choices=["laplacian", "batched", "serving"], default="laplacian")
+    ap.add_argument("--workload", choices=["laplacian", "batched", "serving", "orth"],
+                    default="laplacian")
+    ap.add_argument("--orth-sizes", default="1050,2100,4200",
+                    help="orth: matrix orders (multiples of 21)")
     ap.add_argument("--count", type=int, default=4096, help="batched: number of problems")
     ap.add_argument("--plain-count", type=int, default=4096,
                     help="batched: plain calls actually timed (rest extrapolated)")
@@ -364,6 +451,8 @@ def main() -> int:
         return batched_bench(args.count, args.plain_count, not args.no_autotune)
     if args.workload == "serving":
         return serving_bench(args.requests, args.qps, args.budget_gib, args.lanes)
+    if args.workload == "orth":
+        return orth_bench([int(x) for x in args.orth_sizes.split(",")])
 
     import numpy as np
     import torch

@@ -61,12 +61,24 @@ extern "C" {
 #define TE_ERR_NO_DEVICE (-1001)  /* no usable gfx950 device                     */
 #define TE_ERR_WORKSPACE (-1002)  /* workspace too small / allocation failed     */
 #define TE_ERR_KERNEL (-1003)     /* a cooperative chain barrier timed out       */
+#define TE_ERR_UNSUPPORTED (-1004) /* the options do not apply to this input:
+                                      orth = TE_ORTH_MGS with n > TE_MGS_MAX_N   */
+
+/* Re-orthogonalization inside a cluster (te_opts.orth).
+ * TE_ORTH_CWY: compact WY, the paper's method (Alg. 4 with section 3.3.2).
+ * TE_ORTH_MGS: modified Gram-Schmidt against the earlier members' unit
+ *   vectors after every solve, the DSTEIN scheme the paper starts from and
+ *   compares against (Alg. 1).  Each chain runs in one workgroup with the
+ *   iterate in registers, so it takes problems of order n <= TE_MGS_MAX_N. */
+#define TE_ORTH_CWY 0
+#define TE_ORTH_MGS 1
+#define TE_MGS_MAX_N 8192
 
 /* Options for the _ex entry point.  Zero-initialize and set what you need;
  * a zero field means the default. */
 typedef struct te_opts {
     int iters;          /* inverse-iteration steps per vector (default 3)          */
-    int _reserved0;
+    int orth;           /* TE_ORTH_CWY (default) or TE_ORTH_MGS                     */
     uint64_t seed;      /* start-vector seed (default TE_DEFAULT_SEED)              */
     double cluster_rtol;/* cluster gap as a multiple of ||T||_1 (default 1e-3)      */
     int coop_wgs;       /* cap on cooperative workgroups (0: fill the device)       */
@@ -136,7 +148,9 @@ int tridiag_eigvecs_batched(const double *d_all, const double *e_all, const int6
  * chains' sums have one fixed order whatever the workgroup size).  Since a
  * chain never spreads over several workgroups here, this path suits batches of
  * many moderate problems (the cooperative multi-workgroup chain of the other
- * entry points is not used). */
+ * entry points is not used).  The graph path runs the compact-WY method only:
+ * opts with orth = TE_ORTH_MGS make te_batch_graph_create and
+ * te_batch_autotune fail with TE_ERR_UNSUPPORTED. */
 
 /* Launch configuration of the chain kernel of the graph path.
  * chain_threads: threads per chain workgroup (256 or 512).

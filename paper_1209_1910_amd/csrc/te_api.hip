@@ -227,8 +227,9 @@ void plan_groups(const std::vector<ChainItem> &items, const std::vector<double> 
 }  // namespace
 
 Resolved resolve(const te_opts *o) {
-  Resolved r{TE_DEFAULT_ITERS, TE_DEFAULT_SEED, 1e-3, 0, 0};
+  Resolved r{TE_DEFAULT_ITERS, TE_DEFAULT_SEED, 1e-3, 0, 0, TE_ORTH_CWY};
   if (o) {
+    r.orth = o->orth;
     if (o->iters > 0) r.iters = o->iters;
     if (o->seed) r.seed = o->seed;
     if (o->cluster_rtol > 0.0) r.rtol = o->cluster_rtol;
@@ -258,6 +259,7 @@ DeviceLimits limits() {
     L.device = dev;
     L.coop = coop_max_wgs(dev);
     L.small = small_max_wgs(dev);
+    L.mgs = mgs_max_wgs(dev);
     cache[dev] = L;
   }
   return cache[dev];
@@ -406,6 +408,12 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   const int nprob = (int)pd.size();
   DeviceLimits lim = limits();
   if (lim.device < 0 || lim.coop <= 0 || lim.small <= 0) return TE_ERR_NO_DEVICE;
+  const bool mgs = opt.orth == TE_ORTH_MGS;
+  if (mgs) {
+    if (lim.mgs <= 0) return TE_ERR_NO_DEVICE;
+    for (const auto &D : pd)
+      if (D.n > TE_MGS_MAX_N) return TE_ERR_UNSUPPORTED;
+  }
   SharedHold hold;
 
   Run R;
@@ -529,7 +537,8 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
       if (csz[b][c] < 2) continue;
       ChainItem it{b, cst[b][c], csz[b][c], 0};
       const double cost = (double)csz[b][c] * csz[b][c] * R.hp[b].n;
-      if ((size_t)csz[b][c] * (size_t)R.hp[b].n >= kLargeEntries) {
+      // MGS chains all run one per workgroup
+      if (!mgs && (size_t)csz[b][c] * (size_t)R.hp[b].n >= kLargeEntries) {
         large_items.push_back(it);
         large_cost.push_back(cost);
       } else {
@@ -552,7 +561,7 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   std::vector<int> wg_group;
   std::vector<ChainItem> large_ordered;
   plan_groups(large_items, large_cost, coop_nwg, groups, wg_group, large_ordered);
-  const int small_nwg = std::min((int)small_items.size(), lim.small);
+  const int small_nwg = std::min((int)small_items.size(), mgs ? lim.mgs : lim.small);
   const int nslots = std::max(small_nwg, (int)groups.size());
   const int nitems = (int)(small_items.size() + large_ordered.size());
 
@@ -583,8 +592,12 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   TE_CHECK(launch_fill_i32(dflags, 2, 0, stream));
   if (small_nwg > 0) {
     tm.begin(PH_SMALL);
-    TE_CHECK(launch_chain_small(R.dprobs, ditems, (int)small_items.size(), dflags + 1, dflags, scr,
-                                small_nwg, opt.iters, stream));
+    if (mgs)
+      TE_CHECK(launch_chain_mgs(R.dprobs, ditems, (int)small_items.size(), nullptr, dflags + 1,
+                                dflags, scr, small_nwg, opt.iters, stream));
+    else
+      TE_CHECK(launch_chain_small(R.dprobs, ditems, (int)small_items.size(), dflags + 1, dflags,
+                                  scr, small_nwg, opt.iters, stream));
     tm.end();
   }
   if (!groups.empty()) {
@@ -630,7 +643,7 @@ size_t problems_bytes(const std::vector<ProblemDesc> &pd, size_t b0, size_t b1,
     mmax = std::max(mmax, m);
     msum += m;
   }
-  return bytes + chain_bytes(nmax, mmax, std::max(lim.small, lim.coop), lim.coop, msum);
+  return bytes + chain_bytes(nmax, mmax, std::max({lim.small, lim.coop, lim.mgs}), lim.coop, msum);
 }
 
 uint64_t default_budget() {
@@ -673,7 +686,8 @@ int batch_descs(const double *d_all, const double *e_all, const int64_t *off, co
   if (!Z_all) return -8;
   if (!zoff) return -9;
   if (B < 1) return -10;
-  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0)) return -11;
+  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return -11;
   pd.assign((size_t)B, ProblemDesc{});
   bool any_e = false;
   for (int b = 0; b < B; b++) {
@@ -1110,7 +1124,8 @@ int tridiag_eigvecs_ex(const double *d, const double *e, int n, int il, int iu,
   if (!W) return -7;
   if (!Z) return -8;
   if (ldz < n) return -9;
-  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0)) return -10;
+  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return -10;
   if (!ws) return -11;
   if (ws_bytes < tridiag_eigvecs_workspace_bytes(n, il, iu)) return -12;
   if (((uintptr_t)ws) % kAlign) return -11;
@@ -1206,6 +1221,7 @@ te_batch_graph *te_batch_graph_create(const double *d_all, const double *e_all, 
   try {
     std::vector<te::ProblemDesc> pd;
     r = te::batch_descs(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff, B, opt, pd);
+    if (r == 0 && opt && opt->orth != TE_ORTH_CWY) r = TE_ERR_UNSUPPORTED;
     if (r == 0) {
       const te::DeviceLimits lim = te::limits();
       if (lim.device < 0 || lim.small <= 0) {
@@ -1274,6 +1290,7 @@ int te_batch_autotune(const double *d_all, const double *e_all, const int64_t *o
   std::vector<te::ProblemDesc> pd;
   int r = te::batch_descs(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff, B, opt, pd);
   if (r) return r;
+  if (opt && opt->orth != TE_ORTH_CWY) return TE_ERR_UNSUPPORTED;
   const te::DeviceLimits lim = te::limits();
   if (lim.device < 0 || lim.small <= 0) return TE_ERR_NO_DEVICE;
   // Sample: every stride-th problem, at most about 512 problems.

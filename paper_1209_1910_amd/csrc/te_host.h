@@ -22,6 +22,7 @@ struct Resolved {
   double rtol;
   int coop_wgs;
   uint64_t ws_budget;
+  int orth;       // TE_ORTH_CWY or TE_ORTH_MGS
 };
 Resolved resolve(const te_opts *o);
 
@@ -29,6 +30,7 @@ struct DeviceLimits {
   int device = -1;
   int coop = 0;   // co-resident chain workgroups (cooperative kernel)
   int small = 0;  // resident workgroups of the small-chain kernel
+  int mgs = 0;    // resident workgroups of the MGS chain kernel
 };
 DeviceLimits limits();
 

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/tridiag_eigvecs.h"
+
 namespace te {
 
 constexpr int kWave = 64;            // CDNA wavefront width
@@ -113,6 +115,12 @@ hipError_t launch_chain_small_dev(const Prob *probs, const ChainItem *items, int
 constexpr int kPlanBins = 64;
 hipError_t launch_plan(const Prob *probs, int nprob, int *bins, ChainItem *items, int *nitems,
                        hipStream_t s);
+// MGS chains (Alg. 1), one 512-thread workgroup per cluster; item count as
+// for launch_chain_small_dev.  Problems of order n <= TE_MGS_MAX_N.
+hipError_t launch_chain_mgs(const Prob *probs, const ChainItem *items, int nitems_cap,
+                            const int *nitems_dev, int *counter, int *abort_flag,
+                            ChainScratch scr, int nwg, int iters, hipStream_t s);
+int mgs_max_wgs(int device);
 hipError_t launch_finalize(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
                            hipStream_t s);
 hipError_t launch_fill_i32(int *p, size_t n, int v, hipStream_t s);

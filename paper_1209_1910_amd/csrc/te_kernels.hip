@@ -695,6 +695,63 @@ __device__ __forceinline__ double wave_dot(const double *a_, const double *b_, i
   return wave_sum((a0 + a1) + (a2 + a3));
 }
 
+// R dot products a_r . b over [lo, hi) with a_r = a + r * stride (every a_r
+// with the 16-byte alignment of a), each with exactly wave_dot's arithmetic,
+// so each result has wave_dot's bits.  Only rows r < nr (wave-uniform) are
+// read.  Several short rows in flight per wave hide the load and reduction
+// latency that a row at a time exposes when rows are short.
+template <int R>
+__device__ __forceinline__ void wave_dot_rows(const double *a_, size_t stride, int nr,
+                                              const double *b_, int lo, int hi, int lane,
+                                              double (&out)[R]) {
+  const gdp a = (gdp)a_, b = (gdp)b_;
+  double a0[R], a1[R], a2[R], a3[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) a0[r] = a1[r] = a2[r] = a3[r] = 0.0;
+  if (lo < hi && (reinterpret_cast<uintptr_t>(a_ + lo) & 15)) {
+    if (lane == 0) {
+#pragma unroll
+      for (int r = 0; r < R; r++)
+        if (r < nr) a0[r] = a[(size_t)r * stride + lo] * b[lo];
+    }
+    lo++;
+  }
+  const int np = (hi - lo) >> 1;
+  const gd2p B2 = (gd2p)(b + lo);
+  int p = lane;
+  for (; p + 3 * kWave < np; p += 4 * kWave) {
+    const d2v y0 = B2[p], y1 = B2[p + kWave], y2 = B2[p + 2 * kWave], y3 = B2[p + 3 * kWave];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (r < nr) {
+        const gd2p A2 = (gd2p)(a + (size_t)r * stride + lo);
+        const d2v x0 = A2[p], x1 = A2[p + kWave], x2 = A2[p + 2 * kWave], x3 = A2[p + 3 * kWave];
+        a0[r] = fma(x0.x, y0.x, a0[r]); a0[r] = fma(x0.y, y0.y, a0[r]);
+        a1[r] = fma(x1.x, y1.x, a1[r]); a1[r] = fma(x1.y, y1.y, a1[r]);
+        a2[r] = fma(x2.x, y2.x, a2[r]); a2[r] = fma(x2.y, y2.y, a2[r]);
+        a3[r] = fma(x3.x, y3.x, a3[r]); a3[r] = fma(x3.y, y3.y, a3[r]);
+      }
+    }
+  }
+  for (; p < np; p += kWave) {
+    const d2v y0 = B2[p];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (r < nr) {
+        const d2v x0 = ((gd2p)(a + (size_t)r * stride + lo))[p];
+        a0[r] = fma(x0.x, y0.x, a0[r]); a0[r] = fma(x0.y, y0.y, a0[r]);
+      }
+    }
+  }
+  if (((hi - lo) & 1) && lane == 0) {
+#pragma unroll
+    for (int r = 0; r < R; r++)
+      if (r < nr) a1[r] = fma(a[(size_t)r * stride + hi - 1], b[hi - 1], a1[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; r++) out[r] = wave_sum((a0[r] + a1[r]) + (a2[r] + a3[r]));
+}
+
 // (a.b, a.c) over [lo, hi) with exactly wave_dot's arithmetic for each of the
 // two: one pass over a serves both products bit for bit.
 __device__ __forceinline__ void wave_dot_pair(const double *a_, const double *b_,
@@ -1316,6 +1373,11 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
   return grp_sync<NT>(cx);
 }
 
+// Row passes over short rows (c <= kShortRows columns) keep kRowsInFlight rows
+// per wave in flight (same bits as one row at a time).
+constexpr int kShortRows = 256;
+constexpr int kRowsInFlight = 4;
+
 // Runs the chain of one cluster with the group described by ctx.  Returns
 // false if the run was aborted.
 template <int NT>
@@ -1404,9 +1466,26 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         // P3: u = v_hat - Yhat_c x' over rows c..n-1, the last column's term
         // taken apart: u_i = (v_i - Yhat[i, 0..c-1) . x') - y_{c-1,i} x'_{c-1}
         const double xpc = S.xp[c - 1];
-        for (int i = c + cx.gw; i < n; i += cx.nw) {
-          const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xp, 0, c - 1, lane);
-          if (lane == 0) st_dev(&S.u[i], (vin[i] - acc) - yprev[i] * xpc);
+        if (c <= kShortRows) {   // short rows: kRowsInFlight rows per wave at a time
+          const size_t rs = (size_t)cx.nw * ldm;
+          for (int i0 = c + cx.gw; i0 < n; i0 += kRowsInFlight * cx.nw) {
+            const int nr = min(kRowsInFlight, (n - 1 - i0) / cx.nw + 1);
+            double acc[kRowsInFlight];
+            wave_dot_rows<kRowsInFlight>(cv.Yr + (size_t)i0 * ldm, rs, nr, S.xp, 0, c - 1, lane,
+                                         acc);
+            if (lane == 0) {
+#pragma unroll
+              for (int r = 0; r < kRowsInFlight; r++) {
+                const int i = i0 + r * cx.nw;
+                if (r < nr) st_dev(&S.u[i], (vin[i] - acc[r]) - yprev[i] * xpc);
+              }
+            }
+          }
+        } else {
+          for (int i = c + cx.gw; i < n; i += cx.nw) {
+            const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xp, 0, c - 1, lane);
+            if (lane == 0) st_dev(&S.u[i], (vin[i] - acc) - yprev[i] * xpc);
+          }
         }
       }
       x_ready = false;
@@ -1477,11 +1556,32 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         st_dev(&S.xla[c], acc);
       }
       double *qout = last ? (cv.Z + (size_t)c * cv.ldz) : S.q;
-      for (int t = 0; fold_valid(cx.gw, cx.nw, t, n); t++) {
-        const int i = fold_index(cx.gw, cx.nw, t, n);
-        const int l1 = (i < c ? i : c) + 1;
-        const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xpp, 0, l1, lane);
-        if (lane == 0) st_dev(&qout[i], (i == c) ? acc - 1.0 : acc);
+      if (c <= kShortRows) {   // rows 0..c-1 one at a time, rows c..n-1 (c + 1 entries each) in flight
+        for (int i = cx.gw; i < c; i += cx.nw) {
+          const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xpp, 0, i + 1, lane);
+          if (lane == 0) st_dev(&qout[i], acc);
+        }
+        const size_t rs = (size_t)cx.nw * ldm;
+        for (int i0 = c + cx.gw; i0 < n; i0 += kRowsInFlight * cx.nw) {
+          const int nr = min(kRowsInFlight, (n - 1 - i0) / cx.nw + 1);
+          double acc[kRowsInFlight];
+          wave_dot_rows<kRowsInFlight>(cv.Yr + (size_t)i0 * ldm, rs, nr, S.xpp, 0, c + 1, lane,
+                                       acc);
+          if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < kRowsInFlight; r++) {
+              const int i = i0 + r * cx.nw;
+              if (r < nr) st_dev(&qout[i], (i == c) ? acc[r] - 1.0 : acc[r]);
+            }
+          }
+        }
+      } else {
+        for (int t = 0; fold_valid(cx.gw, cx.nw, t, n); t++) {
+          const int i = fold_index(cx.gw, cx.nw, t, n);
+          const int l1 = (i < c ? i : c) + 1;
+          const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xpp, 0, l1, lane);
+          if (lane == 0) st_dev(&qout[i], (i == c) ? acc - 1.0 : acc);
+        }
       }
       if (last) {
         if (c + 1 < cv.M) {
@@ -1548,6 +1648,180 @@ static const void *small_kernel(int nt) {
     case 512: return (const void *)k_chain_small<512>;
     default: return (const void *)k_chain_small<kSmallThreads>;
   }
+}
+
+// ---------------------------------------------------------------------------
+// The paper's baseline re-orthogonalization, modified Gram-Schmidt (Alg. 1,
+// the DSTEIN scheme): after every solve of member c of a cluster,
+// v <- v - <v, z_r> z_r for r = 0 .. c-1 in order, against the earlier
+// members' final unit vectors.  Each projection needs the result of the one
+// before it, so a member's step is c dependent dot products: one workgroup
+// runs a chain, with v in registers (entry i in thread i mod NT, slot i / NT)
+// and the next column's loads issued ahead of the reduction that closes the
+// current projection.  The solves are those of the compact-WY chain
+// (grp_solve).  Every reduction has one fixed order (wave butterflies, then
+// the wave totals in wave order), so results do not depend on timing.
+// ---------------------------------------------------------------------------
+constexpr int kMgsThreads = 512;
+constexpr int kMgsSlots = 16;   // n <= kMgsThreads * kMgsSlots (TE_MGS_MAX_N)
+static_assert(kMgsThreads * kMgsSlots == TE_MGS_MAX_N, "MGS size limit");
+
+template <int NT, int K>
+__device__ bool run_chain_mgs(Ctx &cx, const Prob &P, const ChainItem &it, const Scr &S,
+                              int iters) {
+  constexpr int NW = NT / kWave;
+  CView cv;
+  const size_t s0 = (size_t)it.start;
+  cv.n = P.n; cv.M = it.size;
+  cv.Y = nullptr; cv.Yr = nullptr; cv.T = nullptr; cv.Tr = nullptr;
+  cv.ldy = 0; cv.ldm = 0;
+  cv.Z = as_global(P.Z + s0 * P.ldz);
+  cv.ldz = (size_t)P.ldz;
+  cv.Lrec = as_global(reinterpret_cast<const double4 *>(P.Lrec) + s0 * P.n);
+  cv.Lswb = as_global(P.Lswb + s0 * P.n);
+  const int n = cv.n, tid = threadIdx.x;
+  __shared__ double s_red[2][NW];
+  int buf = 0;
+  // Workgroup sum in a fixed order; the two buffers alternate, so one
+  // barrier per sum suffices (a buffer is rewritten two sums later, after
+  // every thread has passed the barrier of the sum in between).
+  auto wg_sum = [&](double p) {
+    p = wave_sum(p);
+    if (cx.lane == 0) s_red[buf][cx.wave] = p;
+    __syncthreads();
+    double a = s_red[buf][0];
+#pragma unroll
+    for (int w = 1; w < NW; w++) a += s_red[buf][w];
+    buf ^= 1;
+    return a;
+  };
+  double v[K];
+  for (int c = 1; c < cv.M; c++) {
+    // the raw first solve of member c (written by the parallel solves)
+    const gptr<double> zc = (gptr<double>)(cv.Z + (size_t)c * cv.ldz);
+#pragma unroll
+    for (int t = 0; t < K; t++) {
+      const int i = tid + t * NT;
+      v[t] = i < n ? zc[i] : 0.0;
+    }
+    for (int k = 1; k <= iters; k++) {
+      if (k > 1) {   // normalize and solve Eq. (1)
+        double p = 0.0;
+#pragma unroll
+        for (int t = 0; t < K; t++) {
+          const int i = tid + t * NT;
+          if (i < n) st_dev(&S.q[i], v[t]);
+          p = fma(v[t], v[t], p);
+        }
+        const double ss = wg_sum(p);   // its barrier also orders the stores of q
+        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(ss), false, 0)) return false;
+        const gptr<const double> vg = (gptr<const double>)S.v;
+#pragma unroll
+        for (int t = 0; t < K; t++) {
+          const int i = tid + t * NT;
+          v[t] = i < n ? vg[i] : 0.0;
+        }
+      }
+      // v <- v - <v, z_r> z_r, r = 0 .. c-1 (za: z_r, zb: z_{r+1} in flight)
+      double za[K], zb[K];
+      double p = 0.0;
+      {
+        const gptr<const double> z0 = (gptr<const double>)cv.Z;
+#pragma unroll
+        for (int t = 0; t < K; t++) {
+          const int i = tid + t * NT;
+          za[t] = i < n ? z0[i] : 0.0;
+          p = fma(v[t], za[t], p);
+        }
+      }
+      for (int r = 0; r < c; r++) {
+        const bool more = r + 1 < c;
+        if (more) {
+          const gptr<const double> zn = (gptr<const double>)(cv.Z + (size_t)(r + 1) * cv.ldz);
+#pragma unroll
+          for (int t = 0; t < K; t++) {
+            const int i = tid + t * NT;
+            zb[t] = i < n ? zn[i] : 0.0;
+          }
+        }
+        const double sr = wg_sum(p);
+        p = 0.0;
+        if (more) {
+#pragma unroll
+          for (int t = 0; t < K; t++) {
+            v[t] = fma(-sr, za[t], v[t]);
+            p = fma(v[t], zb[t], p);
+            za[t] = zb[t];
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < K; t++) v[t] = fma(-sr, za[t], v[t]);
+        }
+      }
+    }
+    // z_c = v / ||v||, the unit vector later members project against
+    double p = 0.0;
+#pragma unroll
+    for (int t = 0; t < K; t++) p = fma(v[t], v[t], p);
+    const double nv = sqrt(wg_sum(p));
+#pragma unroll
+    for (int t = 0; t < K; t++) {
+      const int i = tid + t * NT;
+      if (i < n) st_dev(cv.Z + (size_t)c * cv.ldz + i, v[t] / nv);
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// MGS chains: one workgroup per cluster, items taken from a work counter
+// (item count nitems, or *nitems_dev when that is not null).
+__global__ void __launch_bounds__(kMgsThreads) k_chain_mgs(const Prob *__restrict__ probs,
+                                                           const ChainItem *__restrict__ items,
+                                                           int nitems, const int *nitems_dev,
+                                                           int *counter, int *abort_flag,
+                                                           ChainScratch scr, int iters) {
+  __shared__ int s_item;
+  Ctx cx;
+  cx.rank = 0; cx.size = 1; cx.cnt = nullptr; cx.flag = nullptr; cx.gen = 0; cx.sgen = 0;
+  cx.abort_flag = abort_flag;
+  cx.wave = threadIdx.x / kWave; cx.lane = threadIdx.x % kWave;
+  cx.gw = cx.wave; cx.nw = kMgsThreads / kWave;
+  if (nitems_dev) nitems = *nitems_dev;
+  double *base = as_global(scr.base + (size_t)blockIdx.x * scr.stride);
+  for (;;) {
+    if (threadIdx.x == 0)
+      s_item = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                   ? nitems
+                   : atomicAdd(counter, 1);
+    __syncthreads();
+    const int idx = s_item;
+    __syncthreads();
+    if (idx >= nitems) break;
+    const ChainItem it = items[idx];
+    const Prob &P = probs[it.prob];
+    const Scr S = make_scr(base, P.n, P.m, it.start & 1);
+    run_chain_mgs<kMgsThreads, kMgsSlots>(cx, P, it, S, iters);
+  }
+}
+
+hipError_t launch_chain_mgs(const Prob *probs, const ChainItem *items, int nitems_cap,
+                            const int *nitems_dev, int *counter, int *abort_flag,
+                            ChainScratch scr, int nwg, int iters, hipStream_t s) {
+  if (nwg <= 0 || (!nitems_dev && nitems_cap <= 0)) return hipSuccess;
+  hipLaunchKernelGGL(k_chain_mgs, dim3(nwg), dim3(kMgsThreads), 0, s, probs, items, nitems_cap,
+                     nitems_dev, counter, abort_flag, scr, iters);
+  return hipGetLastError();
+}
+
+int mgs_max_wgs(int device) {
+  int ncu = 0, per = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_chain_mgs, kMgsThreads,
+                                                   0) != hipSuccess)
+    return 0;
+  return ncu * per;
 }
 
 hipError_t launch_chain_small(const Prob *probs, const ChainItem *items, int nitems, int *counter,

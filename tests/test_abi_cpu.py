@@ -133,3 +133,26 @@ def test_batch_graph_and_autotune_argument_errors():
     assert L.te_batch_graph_launch(NULL, NULL) == -1
     assert L.te_batch_graph_info(NULL, None, None, None) == -1
     L.te_batch_graph_destroy(NULL)
+
+
+def test_orth_option_is_checked_on_the_host():
+    """te_opts.orth other than TE_ORTH_CWY / TE_ORTH_MGS is an invalid options
+    argument (position 10 of tridiag_eigvecs_ex, 11 of the batched call)."""
+    import numpy as np
+    L = binding.lib()
+    o = binding.te_opts()
+    o.orth = 7
+    assert L.tridiag_eigvecs_ex(P, P, 10, 1, 10, NULL, P, P, 10, ctypes.byref(o), P, 1 << 40,
+                                NULL, NULL) == -10
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    off = np.array([0, 10], dtype=np.int64)
+    il = np.array([1], dtype=np.int32)
+    iu = np.array([10], dtype=np.int32)
+    z = np.array([0], dtype=np.int64)
+    assert L.tridiag_eigvecs_batched(P, P, off.ctypes.data_as(i64p), il.ctypes.data_as(ip),
+                                     iu.ctypes.data_as(ip), P, z.ctypes.data_as(i64p), P,
+                                     z.ctypes.data_as(i64p), 1, ctypes.byref(o), NULL) == -11
+    o.orth = binding.TE_ORTH_MGS
+    assert binding._opts(orth="mgs").orth == binding.TE_ORTH_MGS
+    assert binding._opts().orth == binding.TE_ORTH_CWY
