@@ -695,63 +695,6 @@ __device__ __forceinline__ double wave_dot(const double *a_, const double *b_, i
   return wave_sum((a0 + a1) + (a2 + a3));
 }
 
-// R dot products a_r . b over [lo, hi) with a_r = a + r * stride (every a_r
-// with the 16-byte alignment of a), each with exactly wave_dot's arithmetic,
-// so each result has wave_dot's bits.  Only rows r < nr (wave-uniform) are
-// read.  Several short rows in flight per wave hide the load and reduction
-// latency that a row at a time exposes when rows are short.
-template <int R>
-__device__ __forceinline__ void wave_dot_rows(const double *a_, size_t stride, int nr,
-                                              const double *b_, int lo, int hi, int lane,
-                                              double (&out)[R]) {
-  const gdp a = (gdp)a_, b = (gdp)b_;
-  double a0[R], a1[R], a2[R], a3[R];
-#pragma unroll
-  for (int r = 0; r < R; r++) a0[r] = a1[r] = a2[r] = a3[r] = 0.0;
-  if (lo < hi && (reinterpret_cast<uintptr_t>(a_ + lo) & 15)) {
-    if (lane == 0) {
-#pragma unroll
-      for (int r = 0; r < R; r++)
-        if (r < nr) a0[r] = a[(size_t)r * stride + lo] * b[lo];
-    }
-    lo++;
-  }
-  const int np = (hi - lo) >> 1;
-  const gd2p B2 = (gd2p)(b + lo);
-  int p = lane;
-  for (; p + 3 * kWave < np; p += 4 * kWave) {
-    const d2v y0 = B2[p], y1 = B2[p + kWave], y2 = B2[p + 2 * kWave], y3 = B2[p + 3 * kWave];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-      if (r < nr) {
-        const gd2p A2 = (gd2p)(a + (size_t)r * stride + lo);
-        const d2v x0 = A2[p], x1 = A2[p + kWave], x2 = A2[p + 2 * kWave], x3 = A2[p + 3 * kWave];
-        a0[r] = fma(x0.x, y0.x, a0[r]); a0[r] = fma(x0.y, y0.y, a0[r]);
-        a1[r] = fma(x1.x, y1.x, a1[r]); a1[r] = fma(x1.y, y1.y, a1[r]);
-        a2[r] = fma(x2.x, y2.x, a2[r]); a2[r] = fma(x2.y, y2.y, a2[r]);
-        a3[r] = fma(x3.x, y3.x, a3[r]); a3[r] = fma(x3.y, y3.y, a3[r]);
-      }
-    }
-  }
-  for (; p < np; p += kWave) {
-    const d2v y0 = B2[p];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-      if (r < nr) {
-        const d2v x0 = ((gd2p)(a + (size_t)r * stride + lo))[p];
-        a0[r] = fma(x0.x, y0.x, a0[r]); a0[r] = fma(x0.y, y0.y, a0[r]);
-      }
-    }
-  }
-  if (((hi - lo) & 1) && lane == 0) {
-#pragma unroll
-    for (int r = 0; r < R; r++)
-      if (r < nr) a1[r] = fma(a[(size_t)r * stride + hi - 1], b[hi - 1], a1[r]);
-  }
-#pragma unroll
-  for (int r = 0; r < R; r++) out[r] = wave_sum((a0[r] + a1[r]) + (a2[r] + a3[r]));
-}
-
 // (a.b, a.c) over [lo, hi) with exactly wave_dot's arithmetic for each of the
 // two: one pass over a serves both products bit for bit.
 __device__ __forceinline__ void wave_dot_pair(const double *a_, const double *b_,
@@ -1202,6 +1145,32 @@ __device__ bool p1_overlapped(Ctx &cx, const CView &cv, int c, const double *v, 
 // and xla rides along the overlapped P1's reads of Y; in the second sweep
 // (or after the first, when there is only one) come xpla and upre.
 // Barriers here are among the ranks taking part.  Return false on abort.
+// Row passes (P3, P6) while the cluster has few columns (c <= kShortRows):
+// a wave per row would leave most lanes idle on rows this short, so each
+// thread takes whole rows instead, reading Y column-major (coalesced across
+// the threads; row_dot_cm).  Every chain,
+// whatever kernel or group runs it, takes this path for the same c, so the
+// results still do not depend on where a chain runs.
+constexpr int kShortRows = 256;
+
+// sum_{l < len} Y[i + l ldy] x[l] for one row i of column-major Y, by one
+// thread: eight interleaved partial sums (l mod 8) added pairwise, which keeps
+// the rounding error growth near that of a tree sum.
+__device__ __forceinline__ double row_dot_cm(const double *Y_, size_t ldy, int i,
+                                             const double *x_, int len) {
+  const gdp Y = (gdp)Y_, x = (gdp)x_;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int l = 0;
+  for (; l + 8 <= len; l += 8) {
+#pragma unroll
+    for (int r = 0; r < 8; r++) a[r] = fma(Y[(size_t)(l + r) * ldy + i], x[l + r], a[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < 8; r++)
+    if (l + r < len) a[r] = fma(Y[(size_t)(l + r) * ldy + i], x[l + r], a[r]);
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 template <int NT>
 __device__ Ctx la_sub(const Ctx &cx) {
   Ctx sub = cx;
@@ -1240,9 +1209,16 @@ __device__ bool la_tpass(Ctx &cx, const CView &cv, int c, const Scr &S, bool syn
     ok = grp_sync<NT>(sub);
   }
   if (ok) {
-    for (int i = c + 1 + sub.gw; i < n; i += sub.nw) {
-      const double acc = wave_dot(cv.Yr + (size_t)i * cv.ldm, S.xpla, 0, c, lane);
-      if (lane == 0) st_dev(&S.upre[i], S.vla[i] - acc);
+    // the arithmetic of P3 for member c + 1 (short rows: a thread per row)
+    if (c + 1 <= kShortRows) {
+      const int gtid = sub.rank * NT + (int)threadIdx.x, gthreads = sub.size * NT;
+      for (int i = c + 1 + gtid; i < n; i += gthreads)
+        st_dev(&S.upre[i], S.vla[i] - row_dot_cm(cv.Y, cv.ldy, i, S.xpla, c));
+    } else {
+      for (int i = c + 1 + sub.gw; i < n; i += sub.nw) {
+        const double acc = wave_dot(cv.Yr + (size_t)i * cv.ldm, S.xpla, 0, c, lane);
+        if (lane == 0) st_dev(&S.upre[i], S.vla[i] - acc);
+      }
     }
   }
   cx.sgen = sub.gen;
@@ -1373,10 +1349,6 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
   return grp_sync<NT>(cx);
 }
 
-// Row passes over short rows (c <= kShortRows columns) keep kRowsInFlight rows
-// per wave in flight (same bits as one row at a time).
-constexpr int kShortRows = 256;
-constexpr int kRowsInFlight = 4;
 
 // Runs the chain of one cluster with the group described by ctx.  Returns
 // false if the run was aborted.
@@ -1466,20 +1438,10 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         // P3: u = v_hat - Yhat_c x' over rows c..n-1, the last column's term
         // taken apart: u_i = (v_i - Yhat[i, 0..c-1) . x') - y_{c-1,i} x'_{c-1}
         const double xpc = S.xp[c - 1];
-        if (c <= kShortRows) {   // short rows: kRowsInFlight rows per wave at a time
-          const size_t rs = (size_t)cx.nw * ldm;
-          for (int i0 = c + cx.gw; i0 < n; i0 += kRowsInFlight * cx.nw) {
-            const int nr = min(kRowsInFlight, (n - 1 - i0) / cx.nw + 1);
-            double acc[kRowsInFlight];
-            wave_dot_rows<kRowsInFlight>(cv.Yr + (size_t)i0 * ldm, rs, nr, S.xp, 0, c - 1, lane,
-                                         acc);
-            if (lane == 0) {
-#pragma unroll
-              for (int r = 0; r < kRowsInFlight; r++) {
-                const int i = i0 + r * cx.nw;
-                if (r < nr) st_dev(&S.u[i], (vin[i] - acc[r]) - yprev[i] * xpc);
-              }
-            }
+        if (c <= kShortRows) {   // short rows: one thread per row over column-major Y
+          for (int i = c + gtid; i < n; i += gthreads) {
+            const double acc = row_dot_cm(cv.Y, ldy, i, S.xp, c - 1);
+            st_dev(&S.u[i], (vin[i] - acc) - yprev[i] * xpc);
           }
         } else {
           for (int i = c + cx.gw; i < n; i += cx.nw) {
@@ -1556,24 +1518,10 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         st_dev(&S.xla[c], acc);
       }
       double *qout = last ? (cv.Z + (size_t)c * cv.ldz) : S.q;
-      if (c <= kShortRows) {   // rows 0..c-1 one at a time, rows c..n-1 (c + 1 entries each) in flight
-        for (int i = cx.gw; i < c; i += cx.nw) {
-          const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xpp, 0, i + 1, lane);
-          if (lane == 0) st_dev(&qout[i], acc);
-        }
-        const size_t rs = (size_t)cx.nw * ldm;
-        for (int i0 = c + cx.gw; i0 < n; i0 += kRowsInFlight * cx.nw) {
-          const int nr = min(kRowsInFlight, (n - 1 - i0) / cx.nw + 1);
-          double acc[kRowsInFlight];
-          wave_dot_rows<kRowsInFlight>(cv.Yr + (size_t)i0 * ldm, rs, nr, S.xpp, 0, c + 1, lane,
-                                       acc);
-          if (lane == 0) {
-#pragma unroll
-            for (int r = 0; r < kRowsInFlight; r++) {
-              const int i = i0 + r * cx.nw;
-              if (r < nr) st_dev(&qout[i], (i == c) ? acc[r] - 1.0 : acc[r]);
-            }
-          }
+      if (c <= kShortRows) {   // short rows: one thread per row over column-major Y
+        for (int i = gtid; i < n; i += gthreads) {
+          const double acc = row_dot_cm(cv.Y, ldy, i, S.xpp, (i < c ? i : c) + 1);
+          st_dev(&qout[i], (i == c) ? acc - 1.0 : acc);
         }
       } else {
         for (int t = 0; fold_valid(cx.gw, cx.nw, t, n); t++) {
