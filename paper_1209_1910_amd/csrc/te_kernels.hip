@@ -695,6 +695,63 @@ __device__ __forceinline__ double wave_dot(const double *a_, const double *b_, i
   return wave_sum((a0 + a1) + (a2 + a3));
 }
 
+// R dot products a_r . b over [lo, hi) with a_r = a + r * stride (every a_r
+// with the 16-byte alignment of a), each with exactly wave_dot's arithmetic,
+// so each result has wave_dot's bits.  Only r < nr (wave-uniform) are read.
+// Several dot products in flight per wave hide the load and reduction latency
+// that one at a time exposes.
+template <int R>
+__device__ __forceinline__ void wave_dot_multi(const double *a_, size_t stride, int nr,
+                                               const double *b_, int lo, int hi, int lane,
+                                               double (&out)[R]) {
+  const gdp a = (gdp)a_, b = (gdp)b_;
+  double a0[R], a1[R], a2[R], a3[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) a0[r] = a1[r] = a2[r] = a3[r] = 0.0;
+  if (lo < hi && (reinterpret_cast<uintptr_t>(a_ + lo) & 15)) {
+    if (lane == 0) {
+#pragma unroll
+      for (int r = 0; r < R; r++)
+        if (r < nr) a0[r] = a[(size_t)r * stride + lo] * b[lo];
+    }
+    lo++;
+  }
+  const int np = (hi - lo) >> 1;
+  const gd2p B2 = (gd2p)(b + lo);
+  int p = lane;
+  for (; p + 3 * kWave < np; p += 4 * kWave) {
+    const d2v y0 = B2[p], y1 = B2[p + kWave], y2 = B2[p + 2 * kWave], y3 = B2[p + 3 * kWave];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (r < nr) {
+        const gd2p A2 = (gd2p)(a + (size_t)r * stride + lo);
+        const d2v x0 = A2[p], x1 = A2[p + kWave], x2 = A2[p + 2 * kWave], x3 = A2[p + 3 * kWave];
+        a0[r] = fma(x0.x, y0.x, a0[r]); a0[r] = fma(x0.y, y0.y, a0[r]);
+        a1[r] = fma(x1.x, y1.x, a1[r]); a1[r] = fma(x1.y, y1.y, a1[r]);
+        a2[r] = fma(x2.x, y2.x, a2[r]); a2[r] = fma(x2.y, y2.y, a2[r]);
+        a3[r] = fma(x3.x, y3.x, a3[r]); a3[r] = fma(x3.y, y3.y, a3[r]);
+      }
+    }
+  }
+  for (; p < np; p += kWave) {
+    const d2v y0 = B2[p];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (r < nr) {
+        const d2v x0 = ((gd2p)(a + (size_t)r * stride + lo))[p];
+        a0[r] = fma(x0.x, y0.x, a0[r]); a0[r] = fma(x0.y, y0.y, a0[r]);
+      }
+    }
+  }
+  if (((hi - lo) & 1) && lane == 0) {
+#pragma unroll
+    for (int r = 0; r < R; r++)
+      if (r < nr) a1[r] = fma(a[(size_t)r * stride + hi - 1], b[hi - 1], a1[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; r++) out[r] = wave_sum((a0[r] + a1[r]) + (a2[r] + a3[r]));
+}
+
 // (a.b, a.c) over [lo, hi) with exactly wave_dot's arithmetic for each of the
 // two: one pass over a serves both products bit for bit.
 __device__ __forceinline__ void wave_dot_pair(const double *a_, const double *b_,
@@ -1152,6 +1209,7 @@ __device__ bool p1_overlapped(Ctx &cx, const CView &cv, int c, const double *v, 
 // whatever kernel or group runs it, takes this path for the same c, so the
 // results still do not depend on where a chain runs.
 constexpr int kShortRows = 256;
+constexpr int kColsInFlight = 4;   // column dots per wave at a time while c <= kShortRows
 
 // sum_{l < len} Y[i + l ldy] x[l] for one row i of column-major Y, by one
 // thread: eight interleaved partial sums (l mod 8) added pairwise, which keeps
@@ -1459,13 +1517,33 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
       const double gam = -(alpha >= 0.0 ? 1.0 : -1.0) * beta;
       const double tj = (gam == 0.0) ? 0.0 : 1.0 / (gam * gam - alpha * gam);
       const double yc = alpha - gam;
-      for (int l = cx.gw; l < c; l += cx.nw) {
-        const double *col = cv.Y + (size_t)l * ldy;
-        const double acc = wave_dot(col, S.u, c + 1, n, lane);
-        if (lane == 0) {
-          const double rl = col[c];
-          st_dev(&S.s[l], fma(rl, yc, acc));
-          st_dev(&S.r[l], rl);
+      if (c <= kShortRows) {   // few columns: kColsInFlight per wave (wave_dot's bits)
+        for (int l0 = cx.gw; l0 < c; l0 += kColsInFlight * cx.nw) {
+          const int nr = min(kColsInFlight, (c - 1 - l0) / cx.nw + 1);
+          double acc[kColsInFlight];
+          wave_dot_multi<kColsInFlight>(cv.Y + (size_t)l0 * ldy, (size_t)cx.nw * ldy, nr, S.u,
+                                        c + 1, n, lane, acc);
+          if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < kColsInFlight; r++) {
+              if (r < nr) {
+                const int l = l0 + r * cx.nw;
+                const double rl = cv.Y[(size_t)l * ldy + c];
+                st_dev(&S.s[l], fma(rl, yc, acc[r]));
+                st_dev(&S.r[l], rl);
+              }
+            }
+          }
+        }
+      } else {
+        for (int l = cx.gw; l < c; l += cx.nw) {
+          const double *col = cv.Y + (size_t)l * ldy;
+          const double acc = wave_dot(col, S.u, c + 1, n, lane);
+          if (lane == 0) {
+            const double rl = col[c];
+            st_dev(&S.s[l], fma(rl, yc, acc));
+            st_dev(&S.r[l], rl);
+          }
         }
       }
       {
@@ -1493,15 +1571,51 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
           if (lane == 0) st_dev(&S.xseg[sg], d);
         }
       }
-      for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
-        const int p = fold_index(cx.gw, cx.nw, t, c);
-        double ts, tr;
-        wave_dot2(cv.Tr + (size_t)p * ldm + p, S.s + p, S.r + p, c - p, lane, ts, tr);
-        if (lane == 0) {
+      if (c <= kShortRows) {   // short rows of T: one thread per row p
+        const gdp Tc = (gdp)cv.T, sv = (gdp)S.s, rv = (gdp)S.r;
+        for (int p = gtid; p < c; p += gthreads) {
+          // l = c-1 down to p (the same l across the threads: coalesced), in
+          // eight interleaved partial sums added pairwise
+          double bs[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+          double br[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+          const int len = c - p;
+          int k = 0;
+          for (; k + 8 <= len; k += 8) {
+#pragma unroll
+            for (int r = 0; r < 8; r++) {
+              const int l = c - 1 - (k + r);
+              const double t = Tc[(size_t)p + (size_t)l * ldm];
+              bs[r] = fma(t, sv[l], bs[r]);
+              br[r] = fma(t, rv[l], br[r]);
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < 8; r++) {
+            if (k + r < len) {
+              const int l = c - 1 - (k + r);
+              const double t = Tc[(size_t)p + (size_t)l * ldm];
+              bs[r] = fma(t, sv[l], bs[r]);
+              br[r] = fma(t, rv[l], br[r]);
+            }
+          }
+          const double ts = ((bs[0] + bs[1]) + (bs[2] + bs[3])) + ((bs[4] + bs[5]) + (bs[6] + bs[7]));
+          const double tr = ((br[0] + br[1]) + (br[2] + br[3])) + ((br[4] + br[5]) + (br[6] + br[7]));
           const double th = -tj * ts;
           st_dev(&cv.T[(size_t)p + (size_t)c * ldm], th);
           st_dev(&cv.Tr[(size_t)p * ldm + c], th);
           st_dev(&S.xpp[p], fma(th, yc, tr));
+        }
+      } else {
+        for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
+          const int p = fold_index(cx.gw, cx.nw, t, c);
+          double ts, tr;
+          wave_dot2(cv.Tr + (size_t)p * ldm + p, S.s + p, S.r + p, c - p, lane, ts, tr);
+          if (lane == 0) {
+            const double th = -tj * ts;
+            st_dev(&cv.T[(size_t)p + (size_t)c * ldm], th);
+            st_dev(&cv.Tr[(size_t)p * ldm + c], th);
+            st_dev(&S.xpp[p], fma(th, yc, tr));
+          }
         }
       }
       if (gtid == 0) st_dev(&S.xpp[c], tj * yc);
