@@ -198,8 +198,8 @@ void te_batch_graph_destroy(te_batch_graph *g);
 
 /* Autotuner of the graph path.  Times every candidate configuration
  * (chain_threads 256 and 512, chains_per_cu 1, 2, 4, ... up to each variant's
- * occupancy limit) on a sample of the batch (every (B / 512)-th problem, at
- * least every problem when B < 1024): one warm-up launch and one timed launch
+ * occupancy limit) on a sample of the batch (every (B / 2048)-th problem,
+ * every problem when B < 4096): one warm-up launch and one timed launch
  * of that sample's graph each.  The fastest goes into the process's autotune
  * table under the batch's shape key (ceil log2 of the largest n, ceil log2 of
  * the mean n), and, when the environment variable TE_TUNE_FILE names a file,

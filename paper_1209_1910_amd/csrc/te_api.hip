@@ -1293,8 +1293,10 @@ int te_batch_autotune(const double *d_all, const double *e_all, const int64_t *o
   if (opt && opt->orth != TE_ORTH_CWY) return TE_ERR_UNSUPPORTED;
   const te::DeviceLimits lim = te::limits();
   if (lim.device < 0 || lim.small <= 0) return TE_ERR_NO_DEVICE;
-  // Sample: every stride-th problem, at most about 512 problems.
-  const size_t stride = std::max<size_t>(1, pd.size() / 512);
+  // Sample: every stride-th problem, at most about 2048 problems (enough for
+  // segments as full as the batch's own: with a thinner sample the tuner
+  // favoured one chain per CU, which loses on full segments).
+  const size_t stride = std::max<size_t>(1, pd.size() / 2048);
   std::vector<te::ProblemDesc> sample;
   for (size_t b = 0; b < pd.size(); b += stride) sample.push_back(pd[b]);
   std::vector<te_graph_cfg> cand;
