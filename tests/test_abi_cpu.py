@@ -156,3 +156,25 @@ def test_orth_option_is_checked_on_the_host():
     o.orth = binding.TE_ORTH_MGS
     assert binding._opts(orth="mgs").orth == binding.TE_ORTH_MGS
     assert binding._opts().orth == binding.TE_ORTH_CWY
+
+
+def test_graph_path_rejects_mgs_on_the_host():
+    """The graph path runs compact WY only: MGS options fail with
+    TE_ERR_UNSUPPORTED after the argument checks, before any HIP call."""
+    import numpy as np
+    L = binding.lib()
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    off = np.array([0, 10], dtype=np.int64)
+    il = np.array([1], dtype=np.int32)
+    iu = np.array([10], dtype=np.int32)
+    z = np.array([0], dtype=np.int64)
+    A = (off.ctypes.data_as(i64p), il.ctypes.data_as(ip), iu.ctypes.data_as(ip), P,
+         z.ctypes.data_as(i64p), P, z.ctypes.data_as(i64p), 1)
+    o = binding.te_opts()
+    o.orth = binding.TE_ORTH_MGS
+    rc = ctypes.c_int(0)
+    g = L.te_batch_graph_create(P, P, *A, ctypes.byref(o), None, ctypes.byref(rc))
+    assert not g and rc.value == binding.TE_ERR_UNSUPPORTED
+    assert L.te_batch_autotune(P, P, *A, ctypes.byref(o), None, None, None, 0,
+                               None) == binding.TE_ERR_UNSUPPORTED
