@@ -752,6 +752,69 @@ __device__ __forceinline__ void wave_dot_multi(const double *a_, size_t stride, 
   for (int r = 0; r < R; r++) out[r] = wave_sum((a0[r] + a1[r]) + (a2[r] + a3[r]));
 }
 
+// R dot products a_r[lo_r, hi_r) . b[lo_r, hi_r), each with exactly
+// wave_dot(a_r, b, lo_r, hi_r)'s arithmetic (same bits), in one loop so that
+// the loads and reductions of the R products overlap.  Only r < nr
+// (wave-uniform) are read; the others return 0.
+template <int R>
+__device__ __forceinline__ void wave_dot_var(const double *const (&a_)[R], const double *b_,
+                                             const int (&lo_)[R], const int (&hi_)[R], int nr,
+                                             int lane, double (&out)[R]) {
+  const gdp b = (gdp)b_;
+  double a0[R], a1[R], a2[R], a3[R];
+  int lo[R], np[R];
+  bool mainp[R];
+  int pmax = 0;
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    a0[r] = a1[r] = a2[r] = a3[r] = 0.0;
+    lo[r] = lo_[r];
+    np[r] = 0;
+    mainp[r] = true;
+    if (r < nr) {
+      const gdp a = (gdp)a_[r];
+      if (lo[r] < hi_[r] && (reinterpret_cast<uintptr_t>(a_[r] + lo[r]) & 15)) {
+        if (lane == 0) a0[r] = a[lo[r]] * b[lo[r]];
+        lo[r]++;
+      }
+      np[r] = (hi_[r] - lo[r]) >> 1;
+      pmax = np[r] > pmax ? np[r] : pmax;
+    }
+  }
+  // wave_dot's two loops per product: while p + 3*64 < np, four pairs into
+  // a0..a3; then, from the first p that fails, single pairs into a0
+  for (int p = lane; p < pmax; p += 4 * kWave) {
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (r >= nr) continue;
+      const gd2p A2 = (gd2p)((gdp)a_[r] + lo[r]);
+      const gd2p B2 = (gd2p)(b + lo[r]);
+      if (mainp[r] && p + 3 * kWave < np[r]) {
+        const d2v x0 = A2[p], x1 = A2[p + kWave], x2 = A2[p + 2 * kWave], x3 = A2[p + 3 * kWave];
+        const d2v y0 = B2[p], y1 = B2[p + kWave], y2 = B2[p + 2 * kWave], y3 = B2[p + 3 * kWave];
+        a0[r] = fma(x0.x, y0.x, a0[r]); a0[r] = fma(x0.y, y0.y, a0[r]);
+        a1[r] = fma(x1.x, y1.x, a1[r]); a1[r] = fma(x1.y, y1.y, a1[r]);
+        a2[r] = fma(x2.x, y2.x, a2[r]); a2[r] = fma(x2.y, y2.y, a2[r]);
+        a3[r] = fma(x3.x, y3.x, a3[r]); a3[r] = fma(x3.y, y3.y, a3[r]);
+      } else if (mainp[r]) {
+        mainp[r] = false;
+        for (int q = p; q < np[r]; q += kWave) {
+          const d2v x0 = A2[q], y0 = B2[q];
+          a0[r] = fma(x0.x, y0.x, a0[r]); a0[r] = fma(x0.y, y0.y, a0[r]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    if (r < nr && ((hi_[r] - lo[r]) & 1) && lane == 0) {
+      const gdp a = (gdp)a_[r];
+      a1[r] = fma(a[hi_[r] - 1], b[hi_[r] - 1], a1[r]);
+    }
+    out[r] = (r < nr) ? wave_sum((a0[r] + a1[r]) + (a2[r] + a3[r])) : 0.0;
+  }
+}
+
 // (a.b, a.c) over [lo, hi) with exactly wave_dot's arithmetic for each of the
 // two: one pass over a serves both products bit for bit.
 __device__ __forceinline__ void wave_dot_pair(const double *a_, const double *b_,
@@ -1210,6 +1273,7 @@ __device__ bool p1_overlapped(Ctx &cx, const CView &cv, int c, const double *v, 
 // results still do not depend on where a chain runs.
 constexpr int kShortRows = 256;
 constexpr int kColsInFlight = 4;   // column dots per wave at a time while c <= kShortRows
+constexpr int kColsVar = 2;        // the same for dots of different ranges (Y^T v, T^T x)
 
 // sum_{l < len} Y[i + l ldy] x[l] for one row i of column-major Y, by one
 // thread: eight interleaved partial sums (l mod 8) added pairwise, which keeps
@@ -1480,17 +1544,78 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
       } else {
         // P1: x = Y_c^T v
         if (!x_ready) {
-          for (int l = cx.gw; l < c; l += cx.nw) {
-            const double acc = col_dot_segmented(cv.Y + (size_t)l * ldy, vin, l, n, lane);
-            if (lane == 0) st_dev(&S.x[l], acc);
+          if (c <= kShortRows) {   // few columns: kColsVar per wave (same bits)
+            const int top = (n - 1) / kSegRows;
+            for (int l0 = cx.gw; l0 < c; l0 += kColsVar * cx.nw) {
+              const int nr = min(kColsVar, (c - 1 - l0) / cx.nw + 1);
+              const double *col[kColsVar];
+              int lo[kColsVar], hi[kColsVar];
+              double acc[kColsVar], d[kColsVar];
+#pragma unroll
+              for (int r = 0; r < kColsVar; r++) {
+                col[r] = cv.Y + (size_t)(l0 + r * cx.nw) * ldy;
+                acc[r] = 0.0;
+              }
+              // col_dot_segmented's order: segments from the top, added bottom-up
+              for (int sg = top; sg >= 0; sg--) {
+                int ns = 0;   // columns reaching segment sg (a prefix: l grows with r)
+#pragma unroll
+                for (int r = 0; r < kColsVar; r++) {
+                  const int l = l0 + r * cx.nw;
+                  if (r < nr && sg >= l / kSegRows) ns = r + 1;
+                  lo[r] = sg * kSegRows > l ? sg * kSegRows : l;
+                  hi[r] = (sg + 1) * kSegRows < n ? (sg + 1) * kSegRows : n;
+                }
+                if (ns == 0) break;
+                wave_dot_var<kColsVar>(col, vin, lo, hi, ns, lane, d);
+#pragma unroll
+                for (int r = 0; r < kColsVar; r++)
+                  if (r < ns) acc[r] = (sg == top) ? d[r] : acc[r] + d[r];
+              }
+              if (lane == 0) {
+#pragma unroll
+                for (int r = 0; r < kColsVar; r++)
+                  if (r < nr) st_dev(&S.x[l0 + r * cx.nw], acc[r]);
+              }
+            }
+          } else {
+            for (int l = cx.gw; l < c; l += cx.nw) {
+              const double acc = col_dot_segmented(cv.Y + (size_t)l * ldy, vin, l, n, lane);
+              if (lane == 0) st_dev(&S.x[l], acc);
+            }
           }
           if (!grp_sync<NT>(cx)) return false;
         }
-        // P2: x' = T_c^T x (column l has l + 1 entries: folded assignment)
-        for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
-          const int l = fold_index(cx.gw, cx.nw, t, c);
-          const double acc = wave_dot(cv.T + (size_t)l * ldm, S.x, 0, l + 1, lane);
-          if (lane == 0) st_dev(&S.xp[l], acc);
+        // P2: x' = T_c^T x (column l has l + 1 entries: folded assignment),
+        // kColsVar columns per wave at a time while c is small (same bits)
+        if (c <= kShortRows) {
+          for (int t0 = 0; fold_valid(cx.gw, cx.nw, t0, c); t0 += kColsVar) {
+            const double *col[kColsVar];
+            int lo[kColsVar], hi[kColsVar], ls[kColsVar];
+            double d[kColsVar];
+            int nr = 0;
+#pragma unroll
+            for (int r = 0; r < kColsVar; r++) {
+              const bool ok = fold_valid(cx.gw, cx.nw, t0 + r, c);
+              ls[r] = ok ? fold_index(cx.gw, cx.nw, t0 + r, c) : 0;
+              if (ok && nr == r) nr = r + 1;
+              col[r] = cv.T + (size_t)ls[r] * ldm;
+              lo[r] = 0;
+              hi[r] = ls[r] + 1;
+            }
+            wave_dot_var<kColsVar>(col, S.x, lo, hi, nr, lane, d);
+            if (lane == 0) {
+#pragma unroll
+              for (int r = 0; r < kColsVar; r++)
+                if (r < nr) st_dev(&S.xp[ls[r]], d[r]);
+            }
+          }
+        } else {
+          for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
+            const int l = fold_index(cx.gw, cx.nw, t, c);
+            const double acc = wave_dot(cv.T + (size_t)l * ldm, S.x, 0, l + 1, lane);
+            if (lane == 0) st_dev(&S.xp[l], acc);
+          }
         }
         if (!grp_sync<NT>(cx)) return false;
         // P3: u = v_hat - Yhat_c x' over rows c..n-1, the last column's term
