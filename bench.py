@@ -295,7 +295,7 @@ def orth_bench(sizes) -> int:
     return 0
 
 
-def serving_bench(count: int, qps: float, budget_gib: float, lanes: int) -> int:
+def serving_bench(count: int, qps: float, budget_gib: float, lanes: int, coop_wgs=None) -> int:
     """Serving workload: a Poisson request trace (seed 2) replayed in real
     time into the serving engine, then all at once (saturation), against the
     plain one-problem-per-call path serving the same trace in FIFO order.
@@ -318,13 +318,13 @@ def serving_bench(count: int, qps: float, budget_gib: float, lanes: int) -> int:
 
     # warm-up: module load, device pools
     d0, e0 = inputs.uniform_tridiag(512, 5)
-    with binding.Server(hbm_budget=budget, lanes=lanes) as s:
+    with binding.Server(hbm_budget=budget, lanes=lanes, coop_wgs=coop_wgs) as s:
         s.wait(s.submit(d0, e0))
     W, Z = binding.tridiag_eigvecs(d0, e0)
     torch.cuda.synchronize()
 
     def served(real_time: bool):
-        with binding.Server(hbm_budget=budget, lanes=lanes) as s:
+        with binding.Server(hbm_budget=budget, lanes=lanes, coop_wgs=coop_wgs) as s:
             t0 = time.perf_counter()
             ids = []
             for k, r in enumerate(reqs):
@@ -403,7 +403,7 @@ def serving_bench(count: int, qps: float, budget_gib: float, lanes: int) -> int:
         "config": {"workload": f"serving trace: {count} requests, Poisson {qps} QPS (seed 2), "
                                "n log-uniform [256, 16384], 70% U(-1,1) / 30% glued Wilkinson, "
                                "50% all eigenpairs else a random 10% index range",
-                   "hbm_budget_gib": budget_gib, "lanes": lanes},
+                   "hbm_budget_gib": budget_gib, "lanes": lanes, "coop_wgs": coop_wgs},
         "saturation": {"served_solves_per_s": count / span_s, "plain_solves_per_s": sat_plain,
                        "speedup_vs_plain": (count / span_s) / sat_plain,
                        "served_p50_s": _pct(lat_s, 50), "served_p99_s": _pct(lat_s, 99)},
@@ -440,6 +440,8 @@ def main() -> int:
     ap.add_argument("--qps", type=float, default=1.0, help="serving: arrival rate")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serving: HBM budget")
     ap.add_argument("--lanes", type=int, default=3, help="serving: concurrent rounds")
+    ap.add_argument("--coop-wgs", type=int, default=None,
+                    help="serving: cap on cooperative chain workgroups (default: the server's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the library runs "
@@ -450,7 +452,7 @@ def main() -> int:
     if args.workload == "batched":
         return batched_bench(args.count, args.plain_count, not args.no_autotune)
     if args.workload == "serving":
-        return serving_bench(args.requests, args.qps, args.budget_gib, args.lanes)
+        return serving_bench(args.requests, args.qps, args.budget_gib, args.lanes, args.coop_wgs)
     if args.workload == "orth":
         return orth_bench([int(x) for x in args.orth_sizes.split(",")])
 
