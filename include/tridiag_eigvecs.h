@@ -253,10 +253,10 @@ typedef struct te_server te_server;
 /* Start a server on the current device.  hbm_budget: device bytes that
  * admitted requests may hold at once (0: half the free device memory, at most
  * 64 GiB).  lanes: concurrent rounds (0: 3; at most 64).  opt: as for
- * tridiag_eigvecs_ex (may be NULL); coop_wgs = 0 caps the cooperative chain
- * kernel at three quarters of the device's compute units, so that the other
- * lanes keep running beside it.  Returns NULL if there is no usable device or
- * an argument is invalid. */
+ * tridiag_eigvecs_ex (may be NULL); coop_wgs = 0 lets the cooperative chain
+ * kernel fill the device (a smaller cap leaves compute units to the other
+ * lanes while it runs, at the cost of its own speed).  Returns NULL if there
+ * is no usable device or an argument is invalid. */
 te_server *te_server_create(uint64_t hbm_budget, int lanes, const te_opts *opt);
 
 /* Queue one request: eigenpairs il..iu of T = tridiag(e, d, e) of order n.

@@ -244,9 +244,11 @@ te_server *create_server(const DeviceLimits &lim, uint64_t hbm_budget, int lanes
   S.device = lim.device;
   S.lim = lim;
   S.opt = resolve(opt);
-  // Leave a quarter of the compute units to the other lanes while a round
-  // runs its cooperative chains.
-  if (S.opt.coop_wgs <= 0) S.opt.coop_wgs = std::max(1, lim.coop * 3 / 4);
+  // Cooperative chains fill the device unless the caller caps them: the long
+  // chains of the largest requests dominate a busy server's time, and a
+  // quarter of the CUs left to the other lanes gained them less than it cost
+  // those chains.
+  if (S.opt.coop_wgs <= 0) S.opt.coop_wgs = lim.coop;
   S.budget = hbm_budget ? hbm_budget : default_budget();
   S.t0 = Clock::now();
   const int nl = lanes > 0 ? lanes : kDefaultLanes;
