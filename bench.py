@@ -20,6 +20,8 @@ import platform
 import sys
 import time
 
+T_START = time.time()
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -80,24 +82,63 @@ def chain_alg_bytes(n: int, M: int, iters: int = ITERS) -> float:
     return float(8.0 * iters * per.sum())
 
 
-def cpu_baseline(n_sample: int, n_target: int):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _chain_flops(n: int, k: int, iters: int = ITERS) -> float:
+    """Flops of the compact-WY steps of members 1..k-1 of one cluster (section
+    3.3.2's count: 8 n c - 3 c^2 for member c, per inverse-iteration step)."""
+    import numpy as np
+    c = np.arange(1, k, dtype=np.float64)
+    return float(iters * (8.0 * n * c - 3.0 * c * c).sum())
+
+
+def cpu_baseline(n: int, ks=(160, 224, 288)):
+    """The oracle, single-threaded, on the first k eigenpairs of the same
+    matrix for three k (a range request il = 1 .. iu = k: one cluster of k
+    members, the same arithmetic as the first k members of the full run).
+    Time model t(k) = a k + b F(k), F the compact-WY flop count above; the
+    least-squares fit over the three samples gives t(n) for all n members."""
+    import numpy as np
+
     import oracle
     from paper_1209_1910_amd import inputs
     oracle.build(force=False)
-    d, e = inputs.laplacian_tridiag(n_sample)
-    t0 = time.perf_counter()
-    oracle.eigvecs(d, e)
-    dt = time.perf_counter() - t0
-    scale = (n_target / n_sample) ** 3
+    d, e = inputs.workload_laplacian(n)
+    ts = []
+    for k in ks:
+        t0 = time.perf_counter()
+        oracle.eigvecs(d, e, 1, k)
+        ts.append(time.perf_counter() - t0)
+    from scipy.optimize import nnls
+    A = np.array([[k, _chain_flops(n, k)] for k in ks])
+    sc = A.max(axis=0)
+    (a, b), _ = nnls(A / sc, np.array(ts))
+    a, b = a / sc[0], b / sc[1]
+    t_full = a * n + b * _chain_flops(n, n)
     return {
-        "value": n_target / (dt * scale),
+        "value": n / t_full,
         "unit": "eigvecs/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"full oracle run (bisection, clustering, inverse iteration with compact WY) on "
-                   f"tridiag(-1,2,-1) n={n_sample}, {dt:.1f} s single-threaded on "
-                   f"{platform.processor() or platform.machine()}; time scaled by "
-                   f"(n/{n_sample})^3 to n={n_target} (extrapolated)"),
+        "sample": (f"oracle (bisection, clusters, inverse iteration with compact WY), one thread, "
+                   f"on the first k eigenpairs of tridiag(-1,2,-1) n={n} for k = "
+                   + ", ".join(str(k) for k in ks) + " ("
+                   + ", ".join(f"{t:.1f}" for t in ts) + " s); t(k) = a k + b F(k) with F the "
+                   f"compact-WY flop count fitted by non-negative least squares and evaluated at k = n "
+                   f"({t_full:.0f} s, extrapolated)"),
+        "cpu_model": _cpu_model(),
+        "nproc": os.cpu_count(),
+        "fit": {"a_s_per_member": float(a), "b_s_per_flop": float(b), "t_full_s": float(t_full),
+                "k": list(ks), "t_s": ts},
     }
 
 
@@ -422,8 +463,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=16000)
-    ap.add_argument("--cpu-n", type=int, default=1600,
-                    help="oracle sample size (n >= 1571 keeps the sample a single cluster)")
+    ap.add_argument("--cpu-ks", default="160,224,288",
+                    help="oracle sample: member counts k of the first-k range requests")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock budget from process start; 0 = run every requested call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (profiler counter calibration)")
@@ -471,27 +514,66 @@ def main() -> int:
     e = torch.from_numpy(e_np).to(dev)
     torch.cuda.synchronize()
 
-    print(f"[bench] n={n} warmup={args.warmup}", file=sys.stderr, flush=True)
-    for w in range(args.warmup):
+    # The oracle baseline runs in a host thread beside the untimed warm-up call
+    # (the oracle is a ctypes call, which releases the interpreter lock).
+    cpu = {}
+    cpu_thread = None
+    if not args.no_cpu_baseline:
+        import threading
+        ks = tuple(int(x) for x in args.cpu_ks.split(","))
+
+        def _cpu():
+            try:
+                cpu["r"] = cpu_baseline(n, ks)
+            except Exception as ex:  # reported, never fatal for the GPU measurement
+                cpu["err"] = repr(ex)
+        print(f"[bench] cpu baseline: oracle, first k = {ks} members of n={n}", file=sys.stderr,
+              flush=True)
+        cpu_thread = threading.Thread(target=_cpu, daemon=True)
+        cpu_thread.start()
+
+    # Wall-clock budget (from process start): with a budget, one warm-up call,
+    # and timed calls after the first start only while one more still fits;
+    # the JSON line reports the counts actually run.
+    def fits(t_step):
+        return args.budget_s <= 0 or (time.time() - T_START) + t_step <= args.budget_s
+
+    print(f"[bench] n={n} warmup<={args.warmup} steps<={args.steps} budget={args.budget_s} s",
+          file=sys.stderr, flush=True)
+    warm_run = 0
+    t_step = 0.0
+    # one warm-up call (module load, device pools) is all the timed calls need
+    for w in range(min(args.warmup, 1) if args.budget_s > 0 else args.warmup):
+        t0 = time.perf_counter()
         W, Z = binding.tridiag_eigvecs(d, e)
         torch.cuda.synchronize()
-        print(f"[bench] warmup {w + 1} done", file=sys.stderr, flush=True)
+        t_step = time.perf_counter() - t0
+        warm_run += 1
+        print(f"[bench] warmup {w + 1} done ({t_step:.1f} s)", file=sys.stderr, flush=True)
+    if cpu_thread is not None:
+        cpu_thread.join()
+        print(f"[bench] cpu baseline done", file=sys.stderr, flush=True)
 
     binding.te_timing_reset()
     binding.te_timing_enable(True)
     torch.cuda.synchronize()
+    steps_run = 0
     t0 = time.perf_counter()
     for s in range(args.steps):
+        if s > 0 and not fits((time.perf_counter() - t0) / s):
+            break
         W, Z = binding.tridiag_eigvecs(d, e)
         torch.cuda.synchronize()
-        print(f"[bench] step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
+        steps_run += 1
+        print(f"[bench] step {s + 1}/{args.steps} done ({time.perf_counter() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
     t1 = time.perf_counter()
     binding.te_timing_enable(False)
     phases = binding.te_timing_read()
 
     total = t1 - t0
-    ms_per_step = 1000.0 * total / args.steps
-    value = n * args.steps / total
+    ms_per_step = 1000.0 * total / steps_run
+    value = n * steps_run / total
 
     # cluster structure of this run -> algorithmic bytes of the chain kernel
     norm1 = float(np.max(np.abs(d_np) + np.concatenate([[0.0], np.abs(e_np)])
@@ -509,8 +591,8 @@ def main() -> int:
         "value": value,
         "unit": "eigvecs/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps_run,
+        "warmup": warm_run,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -524,11 +606,13 @@ def main() -> int:
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(n), "alg_bytes_per_launch": alg_bytes,
                      "launch_ms": per_launch_s * 1000.0},
-        "phases_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in phases.items()},
+        "phases_ms_per_step": {k: v[0] / steps_run for k, v in phases.items()},
+        "requested": {"steps": args.steps, "warmup": args.warmup, "budget_s": args.budget_s},
     }
-    if not args.no_cpu_baseline:
-        print(f"[bench] cpu baseline: oracle n={args.cpu_n}", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, n)
+    if "r" in cpu:
+        out["cpu_baseline"] = cpu["r"]
+    elif "err" in cpu:
+        out["cpu_baseline"] = {"error": cpu["err"]}
     print(json.dumps(out), flush=True)
     return 0
 
