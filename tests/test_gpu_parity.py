@@ -7,9 +7,6 @@ subspaces largest principal-angle sine <= 1e-9 against the oracle.
 """
 from __future__ import annotations
 
-import json
-import os
-
 import numpy as np
 import pytest
 
@@ -27,7 +24,6 @@ if not torch.cuda.is_available():
 from paper_1209_1910_amd import binding as B  # noqa: E402
 
 SEED = B.TE_DEFAULT_SEED
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _say(msg):
@@ -109,6 +105,25 @@ def test_laplacian_one_cluster_cooperative_path():
     assert orthogonality(Zg) <= 1e-11
     Wo = O.bisect(d, e)
     assert np.array_equal(Wg, Wo)
+
+
+@pytest.mark.parametrize("iters", [1, 2, 4])
+def test_cooperative_iteration_counts(iters):
+    """The cooperative chain with other iteration counts (the lookahead of
+    the next member's first step splits its work differently for 1, 2 and
+    more iterations) against the oracle with the same count."""
+    d, e = G.laplacian_tridiag(1600)
+    _say(f"laplacian1600 cooperative, iters={iters}")
+    W, Z, _ = B.tridiag_eigvecs_ex(d, e, 1, 1600, iters=iters)
+    torch.cuda.synchronize()
+    Wo, Zo, ncl = O.eigvecs(d, e, iters=iters, seed=SEED)
+    assert ncl == 1
+    Wg, Zg = W.cpu().numpy(), Z.cpu().numpy().T.copy()
+    assert np.array_equal(Wg, Wo)
+    assert np.max(sin_angles(Zg, Zo)) <= 1e-9
+    assert orthogonality(Zg) <= 1e-11
+    if iters >= 2:
+        assert residual(d, e, Wg, Zg) <= 1e-12
 
 
 def test_glued_cooperative_groups_vs_oracle():
@@ -203,22 +218,80 @@ def test_chain_result_independent_of_group_size():
             assert np.array_equal(Z.cpu().numpy().T, Zp), rep
 
 
-def test_full_glued_7980_properties():
-    """Full-size glued Wilkinson matrix (clusters of 380 members).  With a
-    fixed count of 3 iterations the method itself leaves residuals of a few
-    1e-12 on the last members of such clusters: the bar is the oracle's own
-    figure on this input (tests/golden/glued7980_oracle.json, written by
-    tests/golden/make_glued7980_oracle.py from the oracle alone), within a
-    factor of 2 for rounding, and never looser than needed."""
+@pytest.fixture(scope="module")
+def glued7980():
     d, e = G.workload_glued()
-    _say("glued 7980 full")
-    Wg, Zg = _gpu(d, e)
+    _say("glued 7980 full: GPU run")
+    W, Z = B.tridiag_eigvecs(d, e)
+    torch.cuda.synchronize()
+    Gm = Z @ Z.T
+    Gm.diagonal().sub_(1.0)
+    orth = float(Gm.abs().max())
+    del Gm
+    return d, e, W.cpu().numpy(), Z.cpu().numpy().T.copy(), orth
+
+
+def test_full_glued_7980_eigvals_clusters(glued7980):
+    d, e, Wg, _, _ = glued7980
+    _say("glued 7980: eigenvalues and clusters against the oracle")
     Wo = O.bisect(d, e)
     assert np.array_equal(Wg, Wo)
-    with open(os.path.join(GOLDEN, "glued7980_oracle.json")) as f:
-        ref = json.load(f)
-    assert residual(d, e, Wg, Zg) <= max(1e-12, 2.0 * ref["max_residual_rel_norm1"])
-    assert orthogonality(Zg) <= max(1e-11, 2.0 * ref["max_orthogonality"])
+    p = O.setup(d, e)
+    st, sz = O.clusters(Wo, p.tol)
+    assert list(sz) == [380] * 7 + [760] * 7
+    gs, gz = B.tridiag_clusters(Wg, p.tol)
+    assert np.array_equal(gs.cpu().numpy(), st) and np.array_equal(gz.cpu().numpy(), sz)
+
+
+def test_full_glued_7980_residual_orthogonality(glued7980):
+    """Orthogonality at the general bar.  Residuals per Peters-Wilkinson
+    cluster at the bar the subspace tolerance implies: by Davis-Kahan a
+    residual r ||T||_1 on a vector of a cluster whose gap to the rest of the
+    spectrum is g bounds its component outside the cluster by r ||T||_1 / g,
+    so r <= 1e-9 g / ||T||_1 keeps it within the 1e-9 subspace tolerance
+    (never looser than 1e-12 where that is larger).  The general 1e-12 bar
+    does not hold on this matrix for the method itself: inside groups of 380
+    eigenvalues that agree to 1e-12, each member's last re-orthogonalization
+    carries the earlier members' errors, and the oracle's own residual on the
+    lambda ~ 5 cluster ranges from 6.8e-12 to 1.4e-10 over start-vector
+    seeds (tests/golden/glued7980_oracle.json, written from the oracle
+    alone by tests/golden/make_glued7980_oracle.py)."""
+    d, e, Wg, Zg, orth = glued7980
+    _say("glued 7980: residual per cluster, orthogonality")
+    assert orth <= 1e-11, orth
+    p = O.setup(d, e)
+    st, sz = O.clusters(Wg, p.tol)
+    TZ = d[:, None] * Zg
+    TZ[1:] += e[:, None] * Zg[:-1]
+    TZ[:-1] += e[:, None] * Zg[1:]
+    res = np.linalg.norm(TZ - Zg * Wg[None, :], axis=0) / p.norm1
+    worst = []
+    for s, c in zip(st, sz):
+        gaps = [Wg[s] - Wg[s - 1]] if s > 0 else []
+        if s + c < len(Wg):
+            gaps.append(Wg[s + c] - Wg[s + c - 1])
+        bar = max(1e-12, 1e-9 * min(gaps) / p.norm1)
+        r = float(res[s:s + c].max())
+        worst.append((int(s), r, bar))
+        assert r <= bar, (int(s), r, bar)
+    _say("glued 7980: max residual %.2e, per cluster %s" % (
+        res.max(), ", ".join(f"{s}:{r:.1e}/{b:.1e}" for s, r, b in worst)))
+
+
+@pytest.mark.parametrize("il,iu", [(1, 380), (3421, 4180), (7221, 7980)])
+def test_full_glued_7980_cluster_subspace(glued7980, il, iu):
+    """Whole Peters-Wilkinson clusters of the full-size run against the
+    oracle: the oracle computes one cluster from its index range (start
+    vectors are keyed by the global index, so this is the full run's
+    arithmetic for that cluster)."""
+    d, e, Wg, Zg, _ = glued7980
+    _say(f"glued 7980: cluster {il}..{iu} subspace against the oracle")
+    Wo, Zo, ncl = O.eigvecs(d, e, il, iu, seed=SEED)
+    assert ncl == 1
+    assert np.array_equal(Wg[il - 1:iu], Wo)
+    s = subspace_sin(Zg[:, il - 1:iu], Zo)
+    _say(f"glued 7980: cluster {il}..{iu} sin {s:.2e}")
+    assert s <= 1e-9, s
 
 
 def test_full_laplacian_16000_sampled():
@@ -236,6 +309,9 @@ def test_full_laplacian_16000_sampled():
     k = np.arange(1, n + 1)
     lam = 2.0 - 2.0 * np.cos(k * np.pi / (n + 1))
     assert np.max(np.abs(Wg - lam)) <= 8 * np.finfo(float).eps * 4.0
+    # sampled eigenvalues bit-exact against the oracle's bisection
+    for c in cols[::4]:
+        assert Wg[c] == O.bisect(d, e, int(c) + 1, int(c) + 1)[0], c
     assert residual(d, e, Wg[cols], Zs) <= 1e-12
     # orthogonality on the sample against the whole basis
     G_ = (Z @ torch.as_tensor(Zs, device=Z.device)).cpu().numpy()
