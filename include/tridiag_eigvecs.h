@@ -118,6 +118,33 @@ int tridiag_eigvecs_ex(const double *d, const double *e, int n, int il, int iu,
                        const te_opts *opt, void *ws, size_t ws_bytes, int *info,
                        hipStream_t stream);
 
+/* ---- Entry point that allocates nothing ----
+ * For callers that cannot allocate device memory while they run: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same method, arguments and results as tridiag_eigvecs_ex (bit-identical),
+ * without the workspace arguments: the workspace is a fixed device array of
+ * TE_NOALLOC_SCRATCH_BYTES inside the library, one per device, held from the
+ * first call on that device until the process ends.  No device memory is
+ * allocated or freed by the call (host-side planning uses small host
+ * vectors).  Problems whose workspace (tridiag_eigvecs_noalloc_bytes) exceeds
+ * TE_NOALLOC_SCRATCH_BYTES are rejected with TE_ERR_WORKSPACE before anything
+ * is enqueued.  Every call on a device shares that device's array: calls
+ * that overlap in time on one device (several host threads or streams) race
+ * and must be serialized by the caller; a call that has returned has finished
+ * with it (the entry point synchronizes `stream`).
+ * Argument positions: d=1 e=2 n=3 il=4 iu=5 W_given=6 W=7 Z=8 ldz=9 opt=10
+ * info=11. */
+#define TE_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+int tridiag_eigvecs_noalloc(const double *d, const double *e, int n, int il, int iu,
+                            const double *W_given, double *W, double *Z, int ldz,
+                            const te_opts *opt, int *info, hipStream_t stream);
+
+/* Workspace bytes tridiag_eigvecs_noalloc needs for one problem (0 for invalid
+ * sizes); the call accepts the problem when this is at most
+ * TE_NOALLOC_SCRATCH_BYTES. */
+size_t tridiag_eigvecs_noalloc_bytes(int n, int il, int iu);
+
 /* B independent problems, processed together.  Problem b has order
  * n_b = off[b+1] - off[b]; its d entries are d_all[off[b] .. off[b+1]-1] and
  * its e entries e_all[off[b] - b .. off[b+1] - b - 2] (n_b - 1 of them).

@@ -25,7 +25,8 @@ SYMBOLS = ("tridiag_eigvecs", "tridiag_eigvecs_given_w", "tridiag_eigvecs_worksp
            "te_server_times", "te_server_destroy",
            "te_batch_graph_create", "te_batch_graph_launch", "te_batch_graph_info",
            "te_batch_graph_destroy", "te_batch_autotune",
-           "te_timing_enable", "te_timing_reset", "te_timing_read", "te_last_hip_error")
+           "te_timing_enable", "te_timing_reset", "te_timing_read", "te_last_hip_error",
+           "tridiag_eigvecs_noalloc", "tridiag_eigvecs_noalloc_bytes")
 PHASES = ("setup", "bisect", "clusters", "first_solves", "transpose", "chain_small",
           "chain_coop", "finalize")
 
@@ -66,6 +67,10 @@ def lib():
         L.tridiag_eigvecs_workspace_bytes.restype = sz
         L.tridiag_eigvecs_ex.argtypes = [_vp, _vp, i, i, i, _vp, _vp, _vp, i,
                                          ctypes.POINTER(te_opts), _vp, sz, _vp, _vp]
+        L.tridiag_eigvecs_noalloc.argtypes = [_vp, _vp, i, i, i, _vp, _vp, _vp, i,
+                                              ctypes.POINTER(te_opts), _vp, _vp]
+        L.tridiag_eigvecs_noalloc_bytes.argtypes = [i, i, i]
+        L.tridiag_eigvecs_noalloc_bytes.restype = sz
         L.tridiag_eigvecs_batched.argtypes = [_vp, _vp, i64p, ip, ip, _vp, i64p, _vp, i64p, i,
                                               ctypes.POINTER(te_opts), _vp]
         L.tridiag_eigvals.argtypes = [_vp, _vp, i, i, i, _vp, _vp]
@@ -256,6 +261,41 @@ def tridiag_eigvecs_ex(d, e, il=1, iu=None, W_given=None, ws=None, info=None, st
                                   _vp(base + pad), ws.numel() - pad, _vp(info.data_ptr()),
                                   _stream_ptr(stream))
     _check("tridiag_eigvecs_ex", rc)
+    return W[:m], Z[:m], info
+
+
+TE_NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def tridiag_eigvecs_noalloc_bytes(n, il=1, iu=None):
+    return int(lib().tridiag_eigvecs_noalloc_bytes(n, il, n if iu is None else iu))
+
+
+def tridiag_eigvecs_noalloc(d, e, il=1, iu=None, W_given=None, W=None, Z=None, info=None,
+                            stream=None, device="cuda", **opts):
+    """The entry point that allocates no device memory (its workspace is the
+    library's fixed per-device array).  W (m), Z (m x n, row j the vector of
+    W[j]) and info (m + 1 int32) may be passed in preallocated.
+    Returns (W, Z, info)."""
+    torch = _torch()
+    d = _dev_f64(d, device)
+    e = _dev_f64(e, device)
+    n = d.numel()
+    iu = n if iu is None else iu
+    m = iu - il + 1
+    if W is None:
+        W = torch.empty(max(m, 1), dtype=torch.float64, device=d.device)
+    if Z is None:
+        Z = torch.empty((max(m, 1), n), dtype=torch.float64, device=d.device)
+    if info is None:
+        info = torch.zeros(m + 1, dtype=torch.int32, device=d.device)
+    wg = _dev_f64(W_given, device) if W_given is not None else None
+    o = _opts(**opts)
+    rc = lib().tridiag_eigvecs_noalloc(_vp(d.data_ptr()), _vp(e.data_ptr() if e.numel() else 0),
+                                       n, il, iu, _vp(wg.data_ptr() if wg is not None else 0),
+                                       _vp(W.data_ptr()), _vp(Z.data_ptr()), n, ctypes.byref(o),
+                                       _vp(info.data_ptr()), _stream_ptr(stream))
+    _check("tridiag_eigvecs_noalloc", rc)
     return W[:m], Z[:m], info
 
 

@@ -1133,6 +1133,73 @@ int tridiag_eigvecs_ex(const double *d, const double *e, int n, int il, int iu,
   return solve_problems(pd, W_given, resolve(opt), ws, ws_bytes, info, stream);
 }
 
+// ---- Entry point that allocates nothing ----
+// Its workspace is this file-scope device array (one copy per device, kept
+// for the life of the process).  Host code never passes the array's name to a
+// kernel or a copy: its device address is taken once per device with
+// hipGetSymbolAddress and every use goes through that pointer.
+static __device__ __align__(256) unsigned char scratch[TE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (null on failure).
+void *scratch_ptr(int dev, int *rc) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *rc = te::hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+size_t tridiag_eigvecs_noalloc_bytes(int n, int il, int iu) {
+  if (n < 1 || il < 1 || iu < il || iu > n) return 0;
+  const int m = iu - il + 1;
+  te::DeviceLimits lim = te::limits();
+  const int coop = lim.coop > 0 ? lim.coop : 4096;
+  const int small = lim.small > 0 ? lim.small : 4096;
+  // a chain has two or more members, so at most m / 2 chains need a slot
+  const int slots = std::min(std::max(coop, small), std::max(m / 2, 1));
+  return te::fixed_bytes(1) + te::prob_layout(n, m).total() +
+         te::chain_bytes(n, m, slots, coop, m);
+}
+
+int tridiag_eigvecs_noalloc(const double *d, const double *e, int n, int il, int iu,
+                            const double *W_given, double *W, double *Z, int ldz,
+                            const te_opts *opt, int *info, hipStream_t stream) {
+  if (!d) return -1;
+  if (!e && n > 1) return -2;
+  if (n < 1) return -3;
+  if (il < 1 || il > n) return -4;
+  if (iu < il || iu > n) return -5;
+  if (!W) return -7;
+  if (!Z) return -8;
+  if (ldz < n) return -9;
+  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return -10;
+  const size_t need = tridiag_eigvecs_noalloc_bytes(n, il, iu);
+  if (need > TE_NOALLOC_SCRATCH_BYTES) return TE_ERR_WORKSPACE;
+  int dev = -1;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return te::hip_fail(he);
+  if (dev < 0 || dev >= kMaxDevices) return TE_ERR_NO_DEVICE;
+  int rc = 0;
+  void *ws = scratch_ptr(dev, &rc);
+  if (!ws) return rc;
+  std::vector<te::ProblemDesc> pd{{d, e, n, il, iu, W, Z, ldz}};
+  return te::solve_problems(pd, W_given, te::resolve(opt), ws, TE_NOALLOC_SCRATCH_BYTES, info,
+                            stream);
+}
+
 int tridiag_eigvals(const double *d, const double *e, int n, int il, int iu, double *W,
                     hipStream_t stream) {
   if (!d) return -1;

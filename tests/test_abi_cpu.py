@@ -68,6 +68,14 @@ def test_other_entry_points_argument_errors():
     o.iters = 3
     assert L.tridiag_eigvecs_ex(P, P, 10, 1, 10, NULL, P, P, 10, ctypes.byref(o), NULL, 1 << 40,
                                 NULL, NULL) == -11
+    assert L.tridiag_eigvecs_noalloc(NULL, P, 10, 1, 10, NULL, P, P, 10, None, NULL, NULL) == -1
+    assert L.tridiag_eigvecs_noalloc(P, P, 10, 1, 11, NULL, P, P, 10, None, NULL, NULL) == -5
+    assert L.tridiag_eigvecs_noalloc(P, P, 10, 1, 10, NULL, NULL, P, 10, None, NULL, NULL) == -7
+    assert L.tridiag_eigvecs_noalloc(P, P, 10, 1, 10, NULL, P, P, 9, None, NULL, NULL) == -9
+    o.iters = -1
+    assert L.tridiag_eigvecs_noalloc(P, P, 10, 1, 10, NULL, P, P, 10, ctypes.byref(o), NULL,
+                                     NULL) == -10
+    assert L.tridiag_eigvecs_noalloc_bytes(10, 4, 3) == 0
 
 
 def test_server_argument_errors():
