@@ -25,6 +25,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CWY_NEW, CWY_ORDINARY, HOUSEHOLDER, MGS = 0, 1, 2, 3
+# per-vector status bits of eigvecs(..., with_status=True)
+ST_NONFINITE, ST_BREAKDOWN, ST_PIVOT = 1, 2, 4
 DEFAULT_SEED = 0x1209_1910
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -68,13 +70,14 @@ def lib():
         L.or_start_vector.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, _dp]
         L.or_lu.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double,
                             _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_ubyte)]
+        L.or_lu.restype = ctypes.c_int
         L.or_lu_solve.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp,
                                   ctypes.POINTER(ctypes.c_ubyte), _dp, _dp]
         L.or_orthogonalize.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp,
-                                       ctypes.c_int, _dp, _dp, ctypes.c_int]
+                                       ctypes.c_int, _dp, _dp, ctypes.c_int, _ip]
         L.or_eigvecs.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _dp, _dp,
-                                 ctypes.c_int]
+                                 ctypes.c_int, _ip]
         L.or_eigvecs.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -146,14 +149,18 @@ def start_vector(seed: int, kglob: int, n: int) -> np.ndarray:
     return v
 
 
-def lu(d, e, sigma: float, pivthr: float):
+def lu(d, e, sigma: float, pivthr: float, with_count: bool = False):
+    """Factors (u1, u2, u3, l, swap) of T - sigma I; with_count also returns
+    how many pivots were replaced by +-pivthr."""
     d, e = _f64(d), _f64(e)
     n = len(d)
     u1, u2, u3, l = (np.empty(n) for _ in range(4))
     swp = np.empty(n, dtype=np.uint8)
-    lib().or_lu(n, _p(d), _p(e) if len(e) else _p(np.zeros(1)), float(sigma), float(pivthr),
-                _p(u1), _p(u2), _p(u3), _p(l), swp.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
-    return u1, u2, u3, l, swp
+    cnt = lib().or_lu(n, _p(d), _p(e) if len(e) else _p(np.zeros(1)), float(sigma),
+                      float(pivthr), _p(u1), _p(u2), _p(u3), _p(l),
+                      swp.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+    f = (u1, u2, u3, l, swp)
+    return (f, int(cnt)) if with_count else f
 
 
 def lu_solve(factors, b) -> np.ndarray:
@@ -165,22 +172,26 @@ def lu_solve(factors, b) -> np.ndarray:
     return x
 
 
-def orthogonalize(V, variant: int = CWY_NEW):
-    """Incremental orthogonalization of the columns of V; returns (Q, Y, T)."""
+def orthogonalize(V, variant: int = CWY_NEW, with_breakdown: bool = False):
+    """Incremental orthogonalization of the columns of V; returns (Q, Y, T),
+    and with with_breakdown the per-column reflector breakdown flags."""
     V = np.asfortranarray(V, dtype=np.float64)
     n, m = V.shape
     Q = np.zeros((n, m), order="F")
     Y = np.zeros((n, m), order="F")
     T = np.zeros((m, m), order="F")
-    rc = lib().or_orthogonalize(n, m, _p(V), n, _p(Q), n, _p(Y), _p(T), variant)
+    brk = np.zeros(m, dtype=np.int32)
+    rc = lib().or_orthogonalize(n, m, _p(V), n, _p(Q), n, _p(Y), _p(T), variant,
+                                brk.ctypes.data_as(_ip))
     if rc:
         raise ValueError(f"or_orthogonalize failed: {rc}")
-    return Q, Y, T
+    return (Q, Y, T, brk) if with_breakdown else (Q, Y, T)
 
 
 def eigvecs(d, e, il: int = 1, iu: int | None = None, W=None, orth: int = CWY_NEW,
-            iters: int = 3, seed: int = DEFAULT_SEED):
-    """Eigenvectors by inverse iteration; returns (W, Z, nclusters).
+            iters: int = 3, seed: int = DEFAULT_SEED, with_status: bool = False):
+    """Eigenvectors by inverse iteration; returns (W, Z, nclusters), and with
+    with_status the per-vector ST_* bits.
 
     With ``W`` given (ascending) the eigenvalues are taken as input and
     ``il`` is the base of the start-vector key (eigenvalue j uses il + j).
@@ -196,9 +207,10 @@ def eigvecs(d, e, il: int = 1, iu: int | None = None, W=None, orth: int = CWY_NE
     m = iu - il + 1
     Wout = np.empty(m)
     Z = np.zeros((n, m), order="F")
+    st = np.zeros(m, dtype=np.int32)
     ncl = lib().or_eigvecs(n, _p(d), _p(e) if len(e) else _p(np.zeros(1)), il, iu,
                            _p(win) if win is not None else None, orth, iters,
-                           seed & (2**64 - 1), _p(Wout), _p(Z), n)
+                           seed & (2**64 - 1), _p(Wout), _p(Z), n, st.ctypes.data_as(_ip))
     if ncl < 0:
         raise ValueError(f"or_eigvecs failed: {ncl}")
-    return Wout, Z, ncl
+    return (Wout, Z, ncl, st) if with_status else (Wout, Z, ncl)

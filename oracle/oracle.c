@@ -191,12 +191,14 @@ void or_start_vector(uint64_t seed, int64_t kglob, int n, double *v)
 /* elimination with partial pivoting on the tridiagonal matrix, giving        */
 /* P (T - sigma I) = L U with U upper triangular with three diagonals          */
 /* (u1, u2, u3) and unit lower bidiagonal L (multipliers l).  A pivot of      */
-/* magnitude below pivthr is replaced by +-pivthr (sign of the pivot, + for 0) */
+/* magnitude below pivthr is replaced by +-pivthr (sign of the pivot, + for 0); */
+/* returns how many pivots were replaced.                                      */
 /* ------------------------------------------------------------------------- */
 
-void or_lu(int n, const double *d, const double *e, double sigma, double pivthr,
-           double *u1, double *u2, double *u3, double *l, unsigned char *swp)
+int or_lu(int n, const double *d, const double *e, double sigma, double pivthr,
+          double *u1, double *u2, double *u3, double *l, unsigned char *swp)
 {
+    int replaced = 0;                        /* pivots moved to +-pivthr */
     double alpha = d[0] - sigma;             /* active row, column i     */
     double beta = n > 1 ? e[0] : 0.0;        /* active row, column i + 1 */
     for (int i = 0; i < n - 1; i++) {
@@ -205,14 +207,14 @@ void or_lu(int n, const double *d, const double *e, double sigma, double pivthr,
         double b1 = (i + 1 < n - 1) ? e[i + 1] : 0.0;     /* row i+1, col i+2 */
         if (fabs(alpha) >= fabs(b)) {
             double piv = alpha;
-            if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+            if (fabs(piv) < pivthr) { piv = piv < 0.0 ? -pivthr : pivthr; replaced++; }
             u1[i] = piv; u2[i] = beta; u3[i] = 0.0; swp[i] = 0;
             l[i] = b / piv;
             alpha = a1 - l[i] * beta;
             beta = b1;
         } else {
             double piv = b;
-            if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+            if (fabs(piv) < pivthr) { piv = piv < 0.0 ? -pivthr : pivthr; replaced++; }
             u1[i] = piv; u2[i] = a1; u3[i] = b1; swp[i] = 1;
             l[i] = alpha / piv;
             alpha = beta - l[i] * a1;
@@ -220,8 +222,9 @@ void or_lu(int n, const double *d, const double *e, double sigma, double pivthr,
         }
     }
     double piv = alpha;
-    if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+    if (fabs(piv) < pivthr) { piv = piv < 0.0 ? -pivthr : pivthr; replaced++; }
     u1[n - 1] = piv; u2[n - 1] = 0.0; u3[n - 1] = 0.0; l[n - 1] = 0.0; swp[n - 1] = 0;
+    return replaced;
 }
 
 /* x = U^{-1} L^{-1} P b, in place in b.  y is n doubles of scratch. */
@@ -262,9 +265,10 @@ static double sgn(double a) { return a >= 0.0 ? 1.0 : -1.0; }   /* sgn(0) = +1 *
 
 /* Householder vector of u (rows c..n-1 meaningful) as in Eq. (yt):
  * c_j = -sgn(u_jj) ||u_{j:n}||, y = [0; u_jj - c_j; u_{j+1:n}].
- * Reading for ||u_{j:n}|| = 0 (the paper is silent): H = I, i.e. y = 0, t = 0.
+ * Reading for ||u_{j:n}|| = 0 (the paper is silent): H = I, i.e. y = 0, t = 0;
+ * *brk is set to 1 in that case (the breakdown of the reflector), else 0.
  * Writes column c of Y; returns c_j and (through uj) u_jj. */
-static double house_vec(int n, int c, const double *u, double *ycol, double *uj)
+static double house_vec(int n, int c, const double *u, double *ycol, double *uj, int *brk)
 {
     double alpha = u[c];
     double beta = nrm2(n - c, u + c);
@@ -277,104 +281,106 @@ static double house_vec(int n, int c, const double *u, double *ycol, double *uj)
         ycol[c] = alpha - gamma;
     }
     *uj = alpha;
+    *brk = beta == 0.0;
     return gamma;
 }
 
-/* New implementation, section 3.3.2: only rows j..n of u_j are formed, Y is
- * split as [L; Yhat], t_j = 1/(c_j^2 - u_jj c_j), the T column uses only Yhat,
- * and q_j = (Y_j T_j Y_j^T - I) e_j.  The x_j <- T_j^T x_j step printed in
- * that section is read as x_j <- T_j x_j, as Eq. (cwy2) and line 8 of Alg. 3
- * require. */
-static void orth_cwy_new(int n, int c, double *Y, int ldy, double *T, int ldt, double *v,
-                         double *w)
+/* The compact-WY step in the reduced form of section 3.3.2, for member c
+ * (the paper's j = c + 1) against the reflectors of members 0..c-1.
+ *
+ * Y_c = [L; Yhat] splits at row c: L holds rows 0..c-1 (lower triangular with
+ * its diagonal), Yhat rows c..n-1; T_c is upper triangular.  Because every
+ * y_l is zero above row l, only the rows of Q_c^T v at and below c are needed
+ * to build the next reflector, and they are
+ *     u_hat = v_hat - Yhat T_c^T (L^T v_top + Yhat^T v_hat),
+ * with v_top, v_hat the rows of v above and from row c.  Eq. (yt) turns
+ * u_hat into y_c and t_c = 1/(c_j^2 - u_jj c_j).  The new column of T is
+ * -t_c T_c (Y_c^T y_c) = -t_c T_c (Yhat^T y_hat): the L rows of Y_c^T y_c
+ * meet the zero top of y_c.  The iterate is replaced by
+ *     q = (Y_{c+1} T_{c+1} Y_{c+1}^T - I) e_c = Y_{c+1} (T_{c+1} r) - e_c,
+ * r = row c of Y_{c+1}.  The section prints this product with T^T; the form
+ * of Eq. (cwy2) (and of Alg. 3) has T, which is what is used here.
+ * Returns 1 when the reflector breaks down (||u_hat|| = 0), else 0. */
+static int orth_cwy_new(int n, int c, double *Y, int ldy, double *T, int ldt, double *v,
+                        double *w)
 {
-    double *vchk = w;           /* c     */
-    double *tmp = w + n;        /* c     */
-    double *uh = w + 2 * n;     /* n     */
-    double *x = w + 3 * n;      /* c + 1 */
-    double *q = w + 4 * n;      /* n     */
-    /* u_hat <- v_hat (DCOPY); rows c..n-1 of uh are used */
-    for (int i = c; i < n; i++) uh[i] = v[i];
-    /* v_chk <- L^T v_chk (DTRMV, L = rows 0..c-1 of the first c columns) */
+    double *x = w;              /* c: Y_c^T v, then T_c^T of it          */
+    double *tmp = w + n;        /* c + 1                                  */
+    double *uh = w + 2 * n;     /* rows c..n-1: u_hat                     */
+    double *xr = w + 3 * n;     /* c + 1: T_{c+1} r                       */
+    double *q = w + 4 * n;      /* n                                      */
+
+    /* x_l = (Yhat^T v_hat)_l + (L^T v_top)_l, the L part summed first */
     for (int l = 0; l < c; l++) {
-        double s = 0.0;
-        for (int i = l; i < c; i++) s = s + Y[i + (size_t)l * ldy] * v[i];
-        vchk[l] = s;
+        double top = 0.0;
+        for (int i = l; i < c; i++) top = top + Y[i + (size_t)l * ldy] * v[i];
+        double bot = 0.0;
+        for (int i = c; i < n; i++) bot = bot + Y[i + (size_t)l * ldy] * v[i];
+        x[l] = bot + top;
     }
-    /* v_chk <- Yhat^T v_hat + v_chk (DGEMV) */
+    /* x <- T_c^T x */
     for (int l = 0; l < c; l++) {
         double s = 0.0;
-        for (int i = c; i < n; i++) s = s + Y[i + (size_t)l * ldy] * v[i];
-        vchk[l] = s + vchk[l];
-    }
-    /* v_chk <- T^T v_chk (DTRMV, T upper) */
-    for (int l = 0; l < c; l++) {
-        double s = 0.0;
-        for (int p = 0; p <= l; p++) s = s + T[p + (size_t)l * ldt] * vchk[p];
+        for (int p = 0; p <= l; p++) s = s + T[p + (size_t)l * ldt] * x[p];
         tmp[l] = s;
     }
-    for (int l = 0; l < c; l++) vchk[l] = tmp[l];
-    /* u_hat <- -Yhat v_chk + u_hat (DGEMV) */
+    for (int l = 0; l < c; l++) x[l] = tmp[l];
+    /* u_hat = v_hat - Yhat x */
     for (int i = c; i < n; i++) {
         double s = 0.0;
-        for (int l = 0; l < c; l++) s = s + Y[i + (size_t)l * ldy] * vchk[l];
-        uh[i] = uh[i] - s;
+        for (int l = 0; l < c; l++) s = s + Y[i + (size_t)l * ldy] * x[l];
+        uh[i] = v[i] - s;
     }
-    /* y_j and t_j (DCOPY, DNRM2) */
+    /* Eq. (yt): y_c (column c of Y) and t_c */
     double *ycol = Y + (size_t)c * ldy;
     double ujj;
-    double gamma = house_vec(n, c, uh, ycol, &ujj);
-    double tj = gamma == 0.0 ? 0.0 : 1.0 / (gamma * gamma - ujj * gamma);
-    /* t_hat <- (-t_j) Yhat^T y_hat (DGEMV); t_hat <- T t_hat (DTRMV) */
+    int brk;
+    double gamma = house_vec(n, c, uh, ycol, &ujj, &brk);
+    double tc = gamma == 0.0 ? 0.0 : 1.0 / (gamma * gamma - ujj * gamma);
+    /* column c of T: -t_c T_c (Yhat^T y_hat), diagonal t_c */
     for (int l = 0; l < c; l++) {
         double s = 0.0;
         for (int i = c; i < n; i++) s = s + Y[i + (size_t)l * ldy] * ycol[i];
-        tmp[l] = (-tj) * s;
+        tmp[l] = (-tc) * s;
     }
     for (int p = 0; p < c; p++) {
         double s = 0.0;
         for (int l = p; l < c; l++) s = s + T[p + (size_t)l * ldt] * tmp[l];
         T[p + (size_t)c * ldt] = s;
     }
-    T[c + (size_t)c * ldt] = tj;
-    /* x_j <- row j of Y_j (DCOPY); x_j <- T_j x_j (DTRMV) */
-    for (int l = 0; l <= c; l++) x[l] = Y[c + (size_t)l * ldy];
+    T[c + (size_t)c * ldt] = tc;
+    /* xr = T_{c+1} r with r = row c of Y_{c+1} */
 #ifdef OR_PRINTED_TRANSPOSE
     /* Test-only planted mistake: the transposed product as printed. */
     for (int l = 0; l <= c; l++) {
         double s = 0.0;
-        for (int p = 0; p <= l; p++) s = s + T[p + (size_t)l * ldt] * x[p];
-        tmp[l] = s;
+        for (int p = 0; p <= l; p++) s = s + T[p + (size_t)l * ldt] * Y[c + (size_t)p * ldy];
+        xr[l] = s;
     }
 #else
     for (int p = 0; p <= c; p++) {
         double s = 0.0;
-        for (int l = p; l <= c; l++) s = s + T[p + (size_t)l * ldt] * x[l];
-        tmp[p] = s;
+        for (int l = p; l <= c; l++) s = s + T[p + (size_t)l * ldt] * Y[c + (size_t)l * ldy];
+        xr[p] = s;
     }
 #endif
-    for (int p = 0; p <= c; p++) x[p] = tmp[p];
-    /* q_chk <- L_j x_j (DCOPY, DTRMV); q_hat <- Yhat_j x_j (DGEMV) */
-    for (int i = 0; i <= c; i++) {
+    /* q = Y_{c+1} xr - e_c (row i of Y_{c+1} has nonzeros in columns 0..min(i, c)) */
+    for (int i = 0; i < n; i++) {
+        int lmax = i < c ? i : c;
         double s = 0.0;
-        for (int l = 0; l <= i; l++) s = s + Y[i + (size_t)l * ldy] * x[l];
+        for (int l = 0; l <= lmax; l++) s = s + Y[i + (size_t)l * ldy] * xr[l];
         q[i] = s;
     }
-    for (int i = c + 1; i < n; i++) {
-        double s = 0.0;
-        for (int l = 0; l <= c; l++) s = s + Y[i + (size_t)l * ldy] * x[l];
-        q[i] = s;
-    }
-    /* q_jj <- q_jj - 1 */
     q[c] = q[c] - 1.0;
     for (int i = 0; i < n; i++) v[i] = q[i];
+    return brk;
 }
 
 /* Ordinary implementation, section 3.3.1: full-length u_j = v_j - Y T^T Y^T v_j,
  * t_j = 2 / ||y_j||^2, t_hat = T (-t_j Y^T y_j), q_j = e_j - Y_j T_j Y_j^T e_j
  * (again T_j where the section prints T_j^T). */
-static void orth_cwy_ordinary(int n, int c, double *Y, int ldy, double *T, int ldt, double *v,
-                              double *w)
+static int orth_cwy_ordinary(int n, int c, double *Y, int ldy, double *T, int ldt, double *v,
+                             double *w)
 {
     double *vp = w;            /* c + 1 */
     double *tmp = w + n;       /* c + 1 */
@@ -398,7 +404,8 @@ static void orth_cwy_ordinary(int n, int c, double *Y, int ldy, double *T, int l
     }
     double *ycol = Y + (size_t)c * ldy;
     double ujj;
-    house_vec(n, c, u, ycol, &ujj);
+    int brk;
+    house_vec(n, c, u, ycol, &ujj, &brk);
     double ny = nrm2(n, ycol);
     double tj = ny == 0.0 ? 0.0 : 2.0 / (ny * ny);
     for (int l = 0; l < c; l++) {                                  /* DGEMV */
@@ -425,13 +432,14 @@ static void orth_cwy_ordinary(int n, int c, double *Y, int ldy, double *T, int l
         q[i] = q[i] - s;
     }
     for (int i = 0; i < n; i++) v[i] = q[i];
+    return brk;
 }
 
 /* Householder orthogonalization, Alg. 2: apply H_1 .. H_{j-1} one at a time,
  * form y_j, t_j = 2/||y_j||^2 from u_j, then q_j = H_1 ... H_j e_j.  Only the
  * reflector vectors (columns of Y) and their t (diagonal of T) are used. */
-static void orth_householder(int n, int c, double *Y, int ldy, double *T, int ldt, double *v,
-                             double *w)
+static int orth_householder(int n, int c, double *Y, int ldy, double *T, int ldt, double *v,
+                            double *w)
 {
     double *u = w + 2 * n;
     double *q = w + 4 * n;
@@ -445,7 +453,8 @@ static void orth_householder(int n, int c, double *Y, int ldy, double *T, int ld
     }
     double *ycol = Y + (size_t)c * ldy;
     double ujj;
-    house_vec(n, c, u, ycol, &ujj);
+    int brk;
+    house_vec(n, c, u, ycol, &ujj, &brk);
     double ny = nrm2(n, ycol);
     double tj = ny == 0.0 ? 0.0 : 2.0 / (ny * ny);
     T[c + (size_t)c * ldt] = tj;
@@ -458,16 +467,23 @@ static void orth_householder(int n, int c, double *Y, int ldy, double *T, int ld
         for (int i = 0; i < n; i++) q[i] = q[i] - (t * s) * y[i];
     }
     for (int i = 0; i < n; i++) v[i] = q[i];
+    return brk;
 }
 
 enum { OR_CWY_NEW = 0, OR_CWY_ORDINARY = 1, OR_HOUSEHOLDER = 2, OR_MGS = 3 };
+
+/* Per-vector status bits of or_eigvecs: a non-finite entry in the output; a
+ * reflector of one of its orthogonalizations broke down (||u_hat|| = 0, so
+ * H = I); a pivot of its shifted LU fell below eps ||T||_1 and was replaced. */
+enum { OR_ST_NONFINITE = 1, OR_ST_BREAKDOWN = 2, OR_ST_PIVOT = 4 };
 
 /* Householder vector and t of the first vector of a sequence (Alg. 3 line 1). */
 static void orth_first(int n, int variant, double *Y, int ldy, double *T, int ldt,
                        const double *u)
 {
     double ujj;
-    double gamma = house_vec(n, 0, u, Y, &ujj);
+    int brk;
+    double gamma = house_vec(n, 0, u, Y, &ujj, &brk);
     double tj;
     if (variant == OR_CWY_NEW) {
         tj = gamma == 0.0 ? 0.0 : 1.0 / (gamma * gamma - ujj * gamma);
@@ -483,9 +499,10 @@ static void orth_first(int n, int variant, double *Y, int ldy, double *T, int ld
  * given in advance): Q[:, j] from V[:, 0..j].  Y (n x m) and T (m x m) receive
  * the compact-WY factors for the cWY variants (only diag(T) for Householder).
  * variant: 0 new cWY (3.3.2), 1 ordinary cWY (3.3.1), 2 Householder (Alg. 2),
- * 3 MGS. */
+ * 3 MGS.  brk (may be NULL, m entries) receives 1 for a column whose reflector
+ * broke down (||u_hat|| = 0; Householder variants only), else 0. */
 int or_orthogonalize(int n, int m, const double *V, int ldv, double *Q, int ldq,
-                     double *Y, double *T, int variant)
+                     double *Y, double *T, int variant, int *brk)
 {
     if (n < 1 || m < 1 || m > n) return -1;
     double *w = (double *)calloc((size_t)5 * n + 8, sizeof(double));
@@ -495,6 +512,7 @@ int or_orthogonalize(int n, int m, const double *V, int ldv, double *Q, int ldq,
     memset(T, 0, sizeof(double) * (size_t)m * m);
     for (int j = 0; j < m; j++) {
         for (int i = 0; i < n; i++) v[i] = V[i + (size_t)j * ldv];
+        if (brk) brk[j] = 0;
         if (variant == OR_MGS) {
             for (int r = 0; r < j; r++) {
                 double s = 0.0;
@@ -506,7 +524,7 @@ int or_orthogonalize(int n, int m, const double *V, int ldv, double *Q, int ldq,
             continue;
         }
         if (j == 0) {
-            /* Alg. 3 lines 1-3: y_1, t_1 from u_1 = v_1, q_1 = (I - Y_1 T_1 Y_1^T) e_1 */
+            /* first step of Alg. 3: y_1, t_1 from u_1 = v_1, q_1 = (I - Y_1 T_1 Y_1^T) e_1 */
             orth_first(n, variant, Y, n, T, m, v);
             double t = T[0];
             for (int i = 0; i < n; i++) Q[i] = -(t * Y[0]) * Y[i];
@@ -515,9 +533,11 @@ int or_orthogonalize(int n, int m, const double *V, int ldv, double *Q, int ldq,
                 for (int i = 0; i < n; i++) Q[i] = -Q[i];
             continue;
         }
-        if (variant == OR_CWY_NEW) orth_cwy_new(n, j, Y, n, T, m, v, w);
-        else if (variant == OR_CWY_ORDINARY) orth_cwy_ordinary(n, j, Y, n, T, m, v, w);
-        else orth_householder(n, j, Y, n, T, m, v, w);
+        int b;
+        if (variant == OR_CWY_NEW) b = orth_cwy_new(n, j, Y, n, T, m, v, w);
+        else if (variant == OR_CWY_ORDINARY) b = orth_cwy_ordinary(n, j, Y, n, T, m, v, w);
+        else b = orth_householder(n, j, Y, n, T, m, v, w);
+        if (brk) brk[j] = b;
         for (int i = 0; i < n; i++) Q[i + (size_t)j * ldq] = v[i];
     }
     free(w);
@@ -537,9 +557,10 @@ int or_orthogonalize(int n, int m, const double *V, int ldv, double *Q, int ldq,
  * 2 Householder, 3 MGS (Alg. 1).  iters: fixed iteration count (the paper
  * leaves the stop test of the repeat loop open; it is read as a fixed count).  Each output
  * column is normalized to unit 2-norm and its largest-magnitude entry (lowest
- * index on ties) made positive.  Returns the number of clusters, or < 0. */
+ * index on ties) made positive.  status (may be NULL, m entries) receives the
+ * OR_ST_* bits of each vector.  Returns the number of clusters, or < 0. */
 int or_eigvecs(int n, const double *d, const double *e, int il, int iu, const double *Win,
-               int orth, int iters, uint64_t seed, double *W, double *Z, int ldz)
+               int orth, int iters, uint64_t seed, double *W, double *Z, int ldz, int *status)
 {
     if (n < 1 || il < 1 || iu < il || ldz < n) return -1;
     if (!Win && iu > n) return -1;
@@ -571,7 +592,8 @@ int or_eigvecs(int n, const double *d, const double *e, int il, int iu, const do
         int j1 = cst[cl];
         for (int j = j1; j < j1 + csz[cl]; j++) {
             int jc = j - j1;                     /* position in the cluster */
-            or_lu(n, d, e, W[j], p.pivthr, u1, u2, u3, lm, swp);
+            int st = 0;
+            if (or_lu(n, d, e, W[j], p.pivthr, u1, u2, u3, lm, swp) > 0) st |= OR_ST_PIVOT;
             or_start_vector(seed, (int64_t)il + j, n, v);
             for (int k = 1; k <= iters; k++) {
                 double nv = nrm2(n, v);          /* normalize v^(k-1) */
@@ -589,13 +611,17 @@ int or_eigvecs(int n, const double *d, const double *e, int il, int iu, const do
                 }
                 if (jc == 1 && k == 1)           /* Alg. 4: Y_1, T_1 from v_{j1} */
                     orth_first(n, orth, Y, n, T, maxsz, Z + (size_t)j1 * ldz);
-                if (orth == OR_CWY_NEW) orth_cwy_new(n, jc, Y, n, T, maxsz, v, w);
-                else if (orth == OR_CWY_ORDINARY) orth_cwy_ordinary(n, jc, Y, n, T, maxsz, v, w);
-                else orth_householder(n, jc, Y, n, T, maxsz, v, w);
+                int b;
+                if (orth == OR_CWY_NEW) b = orth_cwy_new(n, jc, Y, n, T, maxsz, v, w);
+                else if (orth == OR_CWY_ORDINARY) b = orth_cwy_ordinary(n, jc, Y, n, T, maxsz, v, w);
+                else b = orth_householder(n, jc, Y, n, T, maxsz, v, w);
+                if (b) st |= OR_ST_BREAKDOWN;
             }
             double nv = nrm2(n, v);              /* normalize v^(k) to v_j */
             double *z = Z + (size_t)j * ldz;
             for (int i = 0; i < n; i++) z[i] = v[i] / nv;
+            for (int i = 0; i < n; i++) if (!isfinite(z[i])) { st |= OR_ST_NONFINITE; break; }
+            if (status) status[j] = st;
         }
     }
     /* Output sign: largest-magnitude entry positive (lowest index on ties).

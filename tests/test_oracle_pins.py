@@ -291,14 +291,14 @@ def test_printed_transpose_fails_the_pins():
         L = ctypes.CDLL(so)
         dp = ctypes.POINTER(ctypes.c_double)
         L.or_orthogonalize.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, dp,
-                                       ctypes.c_int, dp, dp, ctypes.c_int]
+                                       ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_void_p]
         n, m = 9, 5
         V = np.asfortranarray(_random_V(n, m, 2))
         Q = np.zeros((n, m), order="F")
         Y = np.zeros((n, m), order="F")
         T = np.zeros((m, m), order="F")
         L.or_orthogonalize(n, m, V.ctypes.data_as(dp), n, Q.ctypes.data_as(dp), n,
-                           Y.ctypes.data_as(dp), T.ctypes.data_as(dp), 0)
+                           Y.ctypes.data_as(dp), T.ctypes.data_as(dp), 0, None)
         assert orthogonality(Q) > 1e-3
     finally:
         shutil.rmtree(tmp)
@@ -406,3 +406,57 @@ def test_given_w_matches_bisection_path():
     W, Z, _ = O.eigvecs(d, e)
     W2, Z2, _ = O.eigvecs(d, e, W=W)
     assert np.array_equal(W, W2) and np.array_equal(Z, Z2)
+
+
+# --- per-vector status bits ------------------------------------------------------------
+
+def test_status_pivot_replaced_at_an_exact_eigenvalue():
+    """Shifting by an exact eigenvalue makes T - lambda I singular: its last
+    pivot is exactly zero and is replaced (the pivot floor); a shift between
+    the eigenvalues replaces nothing.  n = 1: T - d_0 = 0.  n = 2:
+    tridiag(1, 1, 1) has eigenvalues 0 and 2, and the elimination leaves
+    1 - 1 * 1 = 0 and -1 - (-1) * 1 = 0 in the last pivot."""
+    _, _, _, st = O.eigvecs([0.7], [], W=[0.7], with_status=True)
+    assert list(st) == [O.ST_PIVOT]
+    d, e = np.array([1.0, 1.0]), np.array([1.0])
+    _, Z, _, st = O.eigvecs(d, e, W=[0.0, 2.0], with_status=True)
+    assert list(st) == [O.ST_PIVOT, O.ST_PIVOT]
+    assert residual(d, e, np.array([0.0, 2.0]), Z) <= 1e-15
+    _, _, _, st = O.eigvecs(d, e, W=[0.5, 1.5], with_status=True)
+    assert list(st) == [0, 0]
+    (_, cnt) = O.lu(d, e, 0.0, O.setup(d, e).pivthr, with_count=True)
+    assert cnt == 1
+
+
+def test_status_nonfinite_on_the_zero_matrix():
+    """T = 0 has ||T||_1 = 0, so the pivot floor is 0 and the zero pivot is
+    kept: the solve divides by zero and the vector is flagged non-finite."""
+    _, Z, _, st = O.eigvecs([0.0], [], with_status=True)
+    assert list(st) == [O.ST_NONFINITE]
+    assert not np.isfinite(Z).all()
+
+
+@pytest.mark.parametrize("variant", [O.CWY_NEW, O.CWY_ORDINARY, O.HOUSEHOLDER])
+def test_status_reflector_breakdown(variant):
+    """A column already in the span of the earlier ones leaves u_hat = 0: the
+    reflector breaks down (H = I, t = 0).  With V = [e_0, e_0] the first
+    reflector maps e_0 to -e_0 exactly, so u_hat is exactly zero; with
+    independent columns nothing breaks down."""
+    n = 6
+    V = np.zeros((n, 2))
+    V[0, 0] = V[0, 1] = 1.0
+    Q, Y, T, brk = O.orthogonalize(V, variant, with_breakdown=True)
+    assert list(brk) == [0, 1]
+    assert np.all(Y[:, 1] == 0.0) and T[1, 1] == 0.0
+    Q, Y, T, brk = O.orthogonalize(_random_V(n, 4, 3), variant, with_breakdown=True)
+    assert not brk.any()
+
+
+def test_status_of_a_generic_problem():
+    """The status bits are a side output: the vectors are those of the plain
+    call, and no vector of a generic problem breaks down or is non-finite."""
+    d, e = G.uniform_tridiag(200, 3)
+    W, Z, _ = O.eigvecs(d, e)
+    W2, Z2, _, st = O.eigvecs(d, e, with_status=True)
+    assert np.array_equal(W, W2) and np.array_equal(Z, Z2)
+    assert not (st & (O.ST_NONFINITE | O.ST_BREAKDOWN)).any()
