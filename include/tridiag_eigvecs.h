@@ -64,6 +64,20 @@ extern "C" {
 #define TE_ERR_UNSUPPORTED (-1004) /* the options do not apply to this input:
                                       orth = TE_ORTH_MGS with n > TE_MGS_MAX_N   */
 
+/* Per-vector status bits (info[1 + j] of the _ex and _noalloc entry points).
+ * TE_INFO_NONFINITE: the vector has a non-finite entry (or is zero).
+ * TE_INFO_BREAKDOWN: in one of its compact-WY steps the rows of Q^T v from
+ *   the member's own row down were exactly zero (||u_hat|| = 0 in Eq. (yt)):
+ *   no reflector exists, H = I and t = 0 are used, and the iterate becomes the
+ *   next column of the accumulated orthogonal matrix.
+ * TE_INFO_PIVOT: a pivot of the LU of T - lambda_j I (partial pivoting) was
+ *   below eps ||T||_1 in magnitude and was replaced by +-eps ||T||_1; common
+ *   and harmless when lambda_j is accurate to a few ulps (the solve is then
+ *   that of a matrix eps ||T||_1 away). */
+#define TE_INFO_NONFINITE 1
+#define TE_INFO_BREAKDOWN 2
+#define TE_INFO_PIVOT 4
+
 /* Re-orthogonalization inside a cluster (te_opts.orth).
  * TE_ORTH_CWY: compact WY, the paper's method (Alg. 4 with section 3.3.2).
  * TE_ORTH_MGS: modified Gram-Schmidt against the earlier members' unit
@@ -109,8 +123,8 @@ size_t tridiag_eigvecs_workspace_bytes(int n, int il, int iu);
  * of at least tridiag_eigvecs_workspace_bytes(n, il, iu) bytes (256-byte
  * aligned).  If W_given is non-NULL the eigenvalues are taken from it (device,
  * m entries, ascending) and copied to W instead of bisecting.  info (device,
- * may be NULL) receives 1 + m ints: info[0] the number of vectors with a
- * non-finite entry, info[1 + j] nonzero for such a vector.
+ * may be NULL) receives 1 + m ints: info[1 + j] the TE_INFO_* status bits of
+ * vector j, info[0] the number of vectors with any bit set.
  * Argument positions: d=1 e=2 n=3 il=4 iu=5 W_given=6 W=7 Z=8 ldz=9 opt=10
  * ws=11 ws_bytes=12 info=13. */
 int tridiag_eigvecs_ex(const double *d, const double *e, int n, int il, int iu,
@@ -309,6 +323,14 @@ int te_server_wait(te_server *server, int64_t id, int *rc);
  * may be NULL.  Returns as te_server_poll. */
 int te_server_times(te_server *server, int64_t id, double *t_submit, double *t_start,
                     double *t_done);
+
+/* Forget a completed request: the server frees its record (status and
+ * times), after which its id is unknown to poll, wait and times.  A server
+ * keeps every request's record until it is released or the server is
+ * destroyed, so a long-running caller releases each request once it has read
+ * what it needs.  Returns 1 when released, 0 if the request has not completed
+ * yet (nothing is changed), -1 for a NULL server, -2 for an unknown id. */
+int te_server_release(te_server *server, int64_t id);
 
 /* Finish every queued request, stop the lanes and free the server. */
 void te_server_destroy(te_server *server);

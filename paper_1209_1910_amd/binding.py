@@ -19,10 +19,11 @@ TE_DEFAULT_SEED = 0x12091910
 TE_ORTH_CWY, TE_ORTH_MGS = 0, 1        # te_opts.orth: compact WY (Alg. 4) or MGS (Alg. 1)
 TE_MGS_MAX_N = 8192
 TE_ERR_UNSUPPORTED = -1004
+TE_INFO_NONFINITE, TE_INFO_BREAKDOWN, TE_INFO_PIVOT = 1, 2, 4   # info[1 + j] status bits
 SYMBOLS = ("tridiag_eigvecs", "tridiag_eigvecs_given_w", "tridiag_eigvecs_workspace_bytes",
            "tridiag_eigvecs_ex", "tridiag_eigvecs_batched", "tridiag_eigvals", "tridiag_clusters",
            "te_server_create", "te_server_submit", "te_server_poll", "te_server_wait",
-           "te_server_times", "te_server_destroy",
+           "te_server_times", "te_server_destroy", "te_server_release",
            "te_batch_graph_create", "te_batch_graph_launch", "te_batch_graph_info",
            "te_batch_graph_destroy", "te_batch_autotune",
            "te_timing_enable", "te_timing_reset", "te_timing_read", "te_last_hip_error",
@@ -82,6 +83,7 @@ def lib():
         L.te_server_wait.argtypes = [_vp, ctypes.c_int64, ip]
         dp = ctypes.POINTER(ctypes.c_double)
         L.te_server_times.argtypes = [_vp, ctypes.c_int64, dp, dp, dp]
+        L.te_server_release.argtypes = [_vp, ctypes.c_int64]
         L.te_server_destroy.argtypes = [_vp]
         L.te_server_destroy.restype = None
         L.te_timing_enable.argtypes = [i]
@@ -479,13 +481,29 @@ class Server:
         return r == 1
 
     def wait(self, rid):
-        """Block until request rid completes; returns (W, Z) (host arrays)."""
+        """Block until request rid completes; returns (W, Z) (host arrays),
+        which the server object then no longer holds."""
         rc = ctypes.c_int(0)
         r = lib().te_server_wait(self._h, int(rid), ctypes.byref(rc))
         if r < 0:
             raise TeError("te_server_wait", r)
+        out = self._out.pop(int(rid), None)
         _check("te_server request", rc.value)
-        return self._out[int(rid)]
+        return out
+
+    def release(self, rid):
+        """Free the server's record of completed request rid (its status and
+        times); True if released, False if it has not completed yet."""
+        r = lib().te_server_release(self._h, int(rid))
+        if r < 0:
+            raise TeError("te_server_release", r)
+        if r == 1:
+            self._out.pop(int(rid), None)
+        return r == 1
+
+    def held(self):
+        """Requests whose host outputs the server object still holds."""
+        return len(self._out)
 
     def result_code(self, rid):
         rc = ctypes.c_int(0)

@@ -89,12 +89,15 @@ inline size_t even(size_t x) { return (x + 1) & ~(size_t)1; }
 // exceeds this many entries; smaller chains run one per workgroup.
 constexpr size_t kLargeEntries = (size_t)1 << 20;
 
-// Per-problem sizes of the workspace pieces (bytes, each aligned).
+// Per-problem sizes of the workspace pieces (bytes, each aligned).  The
+// interleaved iterate and LU factors (V, Ll, Lu1i, Lu2, Lu3) are read for the
+// last time by k_transpose; Y, Yr, T and Tr are first written by the chain
+// kernels, which run after it on the same stream, so both sets live in one
+// region ("overlay") of the larger of their two sizes.
 struct ProbLayout {
-  size_t e2, nrm, pos, cls, clz, ncl, V, Ll, U1, U2, U3, Sw, Lrec, Lswb, Y, Yr, T, Tr, prm, info;
+  size_t e2, nrm, pos, cls, clz, ncl, V, Y, Yr, T, overlay, Sw, Lrec, Lswb, prm, info;
   size_t total() const {
-    return e2 + nrm + pos + cls + clz + ncl + V + Ll + U1 + U2 + U3 + Sw + Lrec + Lswb + Y + Yr + T +
-           Tr + prm + info;
+    return e2 + nrm + pos + cls + clz + ncl + overlay + Sw + Lrec + Lswb + prm + info;
   }
 };
 
@@ -107,19 +110,15 @@ ProbLayout prob_layout(int n, int m) {
   L.cls = align_up(sizeof(int) * (size_t)m);
   L.clz = align_up(sizeof(int) * (size_t)m);
   L.ncl = align_up(sizeof(int));
-  L.V = align_up(sizeof(double) * nm);
-  L.Ll = L.V;
-  L.U1 = L.V;
-  L.U2 = L.V;
-  L.U3 = L.V;
-  L.Sw = align_up(nm);
-  L.Lrec = align_up(4 * sizeof(double) * nm);
-  L.Lswb = align_up(nm);
+  L.V = align_up(sizeof(double) * nm);   // also each of Ll, Lu1i, Lu2, Lu3
   const size_t ldy = even((size_t)n), ldm = even((size_t)m);
   L.Y = align_up(sizeof(double) * ldy * (size_t)m);
   L.Yr = align_up(sizeof(double) * (size_t)n * ldm);
-  L.T = align_up(sizeof(double) * ldm * ldm);
-  L.Tr = L.T;
+  L.T = align_up(sizeof(double) * ldm * ldm);   // also Tr
+  L.overlay = std::max(5 * L.V, L.Y + L.Yr + 2 * L.T);
+  L.Sw = align_up(nm);
+  L.Lrec = align_up(4 * sizeof(double) * nm);
+  L.Lswb = align_up(nm);
   L.prm = align_up(sizeof(Params));
   L.info = align_up(sizeof(int) * ((size_t)m + 1));
   return L;
@@ -137,6 +136,35 @@ struct Carve {
   }
 };
 
+
+// The workspace arrays of one problem (everything but prm and info), carved
+// in the order of ProbLayout; the overlay region holds V, Ll, Lu1i, Lu2, Lu3
+// and, later in the call, Y, Yr, T, Tr.
+void carve_problem(Carve &cv, Prob &P, int n, int m) {
+  const ProbLayout L = prob_layout(n, m);
+  const size_t nm = (size_t)n * m;
+  P.e2 = cv.take<double>(sizeof(double) * std::max(n - 1, 1));
+  P.nrm = cv.take<double>(sizeof(double) * m);
+  P.pos = cv.take<int>(sizeof(int) * m);
+  P.cl_start = cv.take<int>(sizeof(int) * m);
+  P.cl_size = cv.take<int>(sizeof(int) * m);
+  P.ncl = cv.take<int>(sizeof(int));
+  char *ov = cv.take<char>(L.overlay);
+  P.V = reinterpret_cast<double *>(ov);
+  P.Ll = reinterpret_cast<double *>(ov + L.V);
+  P.Lu1i = reinterpret_cast<double *>(ov + 2 * L.V);
+  P.Lu2 = reinterpret_cast<double *>(ov + 3 * L.V);
+  P.Lu3 = reinterpret_cast<double *>(ov + 4 * L.V);
+  P.ldy = (int)even((size_t)n);
+  P.ldm = (int)even((size_t)m);
+  P.Y = reinterpret_cast<double *>(ov);
+  P.Yr = reinterpret_cast<double *>(ov + L.Y);
+  P.T = reinterpret_cast<double *>(ov + L.Y + L.Yr);
+  P.Tr = reinterpret_cast<double *>(ov + L.Y + L.Yr + L.T);
+  P.Lsw = cv.take<unsigned char>(nm);
+  P.Lrec = cv.take<double>(4 * sizeof(double) * nm);
+  P.Lswb = cv.take<unsigned char>(nm);
+}
 
 // Everything one call needs after the problems are described.
 struct Run {
@@ -447,7 +475,6 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   std::vector<Params> hprm(nprob);
   for (int b = 0; b < nprob; b++) {
     const int n = pd[b].n, m = pd[b].iu - pd[b].il + 1;
-    const size_t nm = (size_t)n * m;
     Prob &P = R.hp[b];
     std::memset(&P, 0, sizeof(P));
     P.d = pd[b].d;
@@ -458,26 +485,7 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
     P.kbase = pd[b].il;
     P.W = pd[b].W;
     P.Z = pd[b].Z;
-    P.e2 = cv.take<double>(sizeof(double) * std::max(n - 1, 1));
-    P.nrm = cv.take<double>(sizeof(double) * m);
-    P.pos = cv.take<int>(sizeof(int) * m);
-    P.cl_start = cv.take<int>(sizeof(int) * m);
-    P.cl_size = cv.take<int>(sizeof(int) * m);
-    P.ncl = cv.take<int>(sizeof(int));
-    P.V = cv.take<double>(sizeof(double) * nm);
-    P.Ll = cv.take<double>(sizeof(double) * nm);
-    P.Lu1i = cv.take<double>(sizeof(double) * nm);
-    P.Lu2 = cv.take<double>(sizeof(double) * nm);
-    P.Lu3 = cv.take<double>(sizeof(double) * nm);
-    P.Lsw = cv.take<unsigned char>(nm);
-    P.Lrec = cv.take<double>(4 * sizeof(double) * nm);
-    P.Lswb = cv.take<unsigned char>(nm);
-    P.ldy = (int)even((size_t)n);
-    P.ldm = (int)even((size_t)m);
-    P.Y = cv.take<double>(sizeof(double) * (size_t)P.ldy * m);
-    P.Yr = cv.take<double>(sizeof(double) * (size_t)n * P.ldm);
-    P.T = cv.take<double>(sizeof(double) * (size_t)P.ldm * P.ldm);
-    P.Tr = cv.take<double>(sizeof(double) * (size_t)P.ldm * P.ldm);
+    carve_problem(cv, P, n, m);
     P.prm = cv.take<Params>(sizeof(Params));
     int *pinfo = cv.take<int>(sizeof(int) * ((size_t)m + 1));
     P.info = (info && nprob == 1) ? info : pinfo;
@@ -797,7 +805,6 @@ int carve_segment(const std::vector<ProblemDesc> &pd, size_t b0, size_t b1, cons
   for (int q = 0; q < nprob; q++) {
     const ProblemDesc &D = pd[b0 + q];
     const int n = D.n, m = D.iu - D.il + 1;
-    const size_t nm = (size_t)n * m;
     loff[q + 1] = loff[q] + m;
     G.nmax = std::max(G.nmax, n);
     G.mmax = std::max(G.mmax, m);
@@ -810,26 +817,7 @@ int carve_segment(const std::vector<ProblemDesc> &pd, size_t b0, size_t b1, cons
     P.info = fx.take<int>(sizeof(int) * ((size_t)m + 1));
     if (!info0) info0 = reinterpret_cast<char *>(P.info);
     info1 = reinterpret_cast<char *>(P.info) + align_up(sizeof(int) * ((size_t)m + 1));
-    P.e2 = sh.take<double>(sizeof(double) * std::max(n - 1, 1));
-    P.nrm = sh.take<double>(sizeof(double) * m);
-    P.pos = sh.take<int>(sizeof(int) * m);
-    P.cl_start = sh.take<int>(sizeof(int) * m);
-    P.cl_size = sh.take<int>(sizeof(int) * m);
-    P.ncl = sh.take<int>(sizeof(int));
-    P.V = sh.take<double>(sizeof(double) * nm);
-    P.Ll = sh.take<double>(sizeof(double) * nm);
-    P.Lu1i = sh.take<double>(sizeof(double) * nm);
-    P.Lu2 = sh.take<double>(sizeof(double) * nm);
-    P.Lu3 = sh.take<double>(sizeof(double) * nm);
-    P.Lsw = sh.take<unsigned char>(nm);
-    P.Lrec = sh.take<double>(4 * sizeof(double) * nm);
-    P.Lswb = sh.take<unsigned char>(nm);
-    P.ldy = (int)even((size_t)n);
-    P.ldm = (int)even((size_t)m);
-    P.Y = sh.take<double>(sizeof(double) * (size_t)P.ldy * m);
-    P.Yr = sh.take<double>(sizeof(double) * (size_t)n * P.ldm);
-    P.T = sh.take<double>(sizeof(double) * (size_t)P.ldm * P.ldm);
-    P.Tr = sh.take<double>(sizeof(double) * (size_t)P.ldm * P.ldm);
+    carve_problem(sh, P, n, m);
     std::memset(&hprm[q], 0, sizeof(Params));
     hprm[q].rtol = opt.rtol;
   }

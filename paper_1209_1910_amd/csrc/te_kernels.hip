@@ -375,6 +375,7 @@ __global__ void __launch_bounds__(256) k_invit(const Prob *__restrict__ probs, i
   const int K = P.pos[j] == 0 ? iters : 1;
   const uint64_t kglob = (uint64_t)(P.kbase + j);
 
+  bool replaced = false;   // a pivot of the LU fell below pivthr
   double ss = 0.0;
   for (int i = 0; i < n; i++) {
     const double v = start_entry(seed, kglob, (uint32_t)i);
@@ -396,7 +397,7 @@ __global__ void __launch_bounds__(256) k_invit(const Prob *__restrict__ probs, i
         unsigned char sw;
         if (fabs(alpha) >= fabs(bi)) {
           piv = alpha;
-          if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+          if (fabs(piv) < pivthr) { piv = piv < 0.0 ? -pivthr : pivthr; replaced = true; }
           u2 = beta; u3 = 0.0; sw = 0;
           l = bi / piv;
           alpha = a1 - l * beta;
@@ -405,7 +406,7 @@ __global__ void __launch_bounds__(256) k_invit(const Prob *__restrict__ probs, i
           cur = bn - l * cur;
         } else {
           piv = bi;
-          if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+          if (fabs(piv) < pivthr) { piv = piv < 0.0 ? -pivthr : pivthr; replaced = true; }
           u2 = a1; u3 = b1; sw = 1;
           l = alpha / piv;
           alpha = beta - l * a1;
@@ -419,11 +420,12 @@ __global__ void __launch_bounds__(256) k_invit(const Prob *__restrict__ probs, i
         V[o] = y * inv;
       }
       double piv = alpha;
-      if (fabs(piv) < pivthr) piv = piv < 0.0 ? -pivthr : pivthr;
+      if (fabs(piv) < pivthr) { piv = piv < 0.0 ? -pivthr : pivthr; replaced = true; }
       const double inv = 1.0 / piv;
       const size_t o = (size_t)(n - 1) * m;
       Ll[o] = 0.0; U1[o] = inv; U2[o] = 0.0; U3[o] = 0.0; SW[o] = 0;
       V[o] = cur * inv;
+      if (P.info) P.info[1 + j] = replaced ? TE_INFO_PIVOT : 0;
     } else {
       for (int i = 0; i < n - 1; i++) {
         const size_t o = (size_t)i * m;
@@ -1642,6 +1644,8 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
       const double gam = -(alpha >= 0.0 ? 1.0 : -1.0) * beta;
       const double tj = (gam == 0.0) ? 0.0 : 1.0 / (gam * gam - alpha * gam);
       const double yc = alpha - gam;
+      if (gam == 0.0 && gtid == 0 && P.info)   // reflector breakdown: H = I
+        P.info[1 + it.start + c] |= TE_INFO_BREAKDOWN;
       if (c <= kShortRows) {   // few columns: kColsInFlight per wave (wave_dot's bits)
         for (int l0 = cx.gw; l0 < c; l0 += kColsInFlight * cx.nw) {
           const int nr = min(kColsInFlight, (c - 1 - l0) / cx.nw + 1);
@@ -2139,7 +2143,9 @@ int device_cus(int device) {
 
 // ---------------------------------------------------------------------------
 // a8: normalize each column, largest-magnitude entry positive (lowest index on
-// ties); flag non-finite vectors.  One wave per column.
+// ties); add the non-finite bit to the vector's status word (the pivot bit
+// came from k_invit, the breakdown bit from the chain) and count the vectors
+// with any bit set.  One wave per column.
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) k_finalize(const Prob *__restrict__ probs, int nprob,
@@ -2172,8 +2178,9 @@ __global__ void __launch_bounds__(256) k_finalize(const Prob *__restrict__ probs
   const double sc = finite ? sgn / sqrt(ss) : 1.0;
   for (int i = lane; i < n; i += kWave) z[i] = z[i] * sc;
   if (P.info && lane == 0) {
-    P.info[1 + j] = finite ? 0 : 1;
-    if (!finite) atomicAdd(P.info, 1);
+    const int st = P.info[1 + j] | (finite ? 0 : TE_INFO_NONFINITE);
+    P.info[1 + j] = st;
+    if (st) atomicAdd(P.info, 1);
   }
 }
 

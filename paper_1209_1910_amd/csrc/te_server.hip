@@ -199,6 +199,10 @@ struct Server {
         std::lock_guard<std::mutex> lk(mu);
         used -= bytes;
         finish(round, rc);
+        for (Request *r : round) {   // the host copies of the inputs are spent
+          std::vector<double>().swap(r->d);
+          std::vector<double>().swap(r->e);
+        }
       }
       cv.notify_all();
     }
@@ -351,6 +355,17 @@ int te_server_times(te_server *srv, int64_t id, double *t_submit, double *t_star
   if (t_start) *t_start = r.t_start;
   if (t_done) *t_done = r.t_done;
   return r.done ? 1 : 0;
+}
+
+int te_server_release(te_server *srv, int64_t id) {
+  if (!srv) return -1;
+  Server &S = srv->s;
+  std::lock_guard<std::mutex> lk(S.mu);
+  auto it = S.all.find(id);
+  if (it == S.all.end()) return -2;
+  if (!it->second->done) return 0;
+  S.all.erase(it);
+  return 1;
 }
 
 void te_server_destroy(te_server *srv) {

@@ -96,6 +96,7 @@ def test_server_argument_errors():
     assert L.te_server_poll(NULL, 1, None) == -1
     assert L.te_server_wait(NULL, 1, None) == -1
     assert L.te_server_times(NULL, 1, None, None, None) == -1
+    assert L.te_server_release(NULL, 1) == -1
     assert not L.te_server_create(0, -1, None)
     assert not L.te_server_create(0, 65, None)
     o = binding.te_opts()

@@ -164,12 +164,48 @@ def test_given_w_and_ex_paths():
     _say("ex")
     W2, Z2, info = B.tridiag_eigvecs_ex(d, e, 1, 400)
     torch.cuda.synchronize()
-    assert int(info[0].item()) == 0
+    _, _, _, st = O.eigvecs(d, e, seed=SEED, with_status=True)
+    info = info.cpu().numpy()
+    assert np.array_equal(info[1:], st) and info[0] == np.count_nonzero(st)
     _compare(d, e, W2.cpu().numpy(), Z2.cpu().numpy().T.copy(), Wo, Zo)
     _say("ex iters=5")
     W3, Z3, _ = B.tridiag_eigvecs_ex(d, e, 1, 400, iters=5, seed=77)
     W5, Z5, _ = O.eigvecs(d, e, iters=5, seed=77)
     _compare(d, e, W3.cpu().numpy(), Z3.cpu().numpy().T.copy(), W5, Z5)
+
+
+STATUS_CASES = {
+    # exact eigenvalue shifts: the last pivot of T - lambda I is exactly zero
+    "n1_exact": (np.array([0.7]), np.array([]), np.array([0.7])),
+    "n2_exact": (np.array([1.0, 1.0]), np.array([1.0]), np.array([0.0, 2.0])),
+    "n2_between": (np.array([1.0, 1.0]), np.array([1.0]), np.array([0.5, 1.5])),
+    # ||T||_1 = 0: the zero pivot is kept and the vector is non-finite
+    "zero": (np.array([0.0]), np.array([]), None),
+    "uniform300": G.uniform_tridiag(300, 7) + (None,),
+    "glued24": G.glued_wilkinson(24, 1e-8) + (None,),
+    "laplacian500": G.laplacian_tridiag(500) + (None,),
+}
+
+
+@pytest.mark.parametrize("name", list(STATUS_CASES))
+def test_status_bits_match_oracle(name):
+    """info[1 + j] carries the same TE_INFO_* bits as the oracle's decisions
+    (pivot replaced in the LU, reflector breakdown, non-finite output) and
+    info[0] counts the flagged vectors."""
+    d, e, Wg = STATUS_CASES[name]
+    _say(f"status bits {name} n={len(d)}")
+    n = len(d)
+    m = n if Wg is None else len(Wg)
+    _, _, info = B.tridiag_eigvecs_ex(d, e, 1, m, W_given=Wg)
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    _, _, _, st = O.eigvecs(d, e, W=Wg, seed=SEED, with_status=True)
+    assert np.array_equal(info[1:], st), (info[1:], st)
+    assert info[0] == np.count_nonzero(st)
+    if name.endswith("exact"):
+        assert np.all(st == B.TE_INFO_PIVOT)
+    if name == "zero":
+        assert list(st) == [B.TE_INFO_NONFINITE]
 
 
 def test_batched_matches_plain():

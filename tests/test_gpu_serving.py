@@ -178,3 +178,23 @@ def test_concurrent_submitters(alone):
         for th in threads:
             th.join()
     assert not errors, errors
+
+
+def test_released_requests_are_forgotten():
+    """A long request stream does not grow the server: each completed request
+    is released once read (its id is then unknown), and wait hands the host
+    outputs to the caller, so neither side keeps per-request state."""
+    d, e = G.uniform_tridiag(64, 3)
+    W0, Z0 = B.tridiag_eigvecs(d, e)
+    torch.cuda.synchronize()
+    W0, Z0 = W0.cpu().numpy(), Z0.cpu().numpy()
+    _say("release: 200 requests")
+    with B.Server(lanes=2) as s:
+        ids = [s.submit(d, e) for _ in range(200)]
+        for rid in ids:
+            W, Z = s.wait(rid)
+            assert np.array_equal(W, W0) and np.array_equal(Z, Z0)
+            assert s.release(rid)
+            with pytest.raises(B.TeError):
+                s.poll(rid)
+        assert s.held() == 0
