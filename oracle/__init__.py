@@ -214,3 +214,40 @@ def eigvecs(d, e, il: int = 1, iu: int | None = None, W=None, orth: int = CWY_NE
     if ncl < 0:
         raise ValueError(f"or_eigvecs failed: {ncl}")
     return (Wout, Z, ncl, st) if with_status else (Wout, Z, ncl)
+
+
+def split_points(d, e) -> np.ndarray:
+    """Block starts of the split matrix (block b is rows bs[b]..bs[b+1]-1)."""
+    d, e = _f64(d), _f64(e)
+    n = len(d)
+    L = lib()
+    L.or_split_points.argtypes = [ctypes.c_int, _dp, _dp, _ip]
+    L.or_split_points.restype = ctypes.c_int
+    bs = np.zeros(n + 1, dtype=np.int32)
+    nb = L.or_split_points(n, _p(d), _p(e) if len(e) else _p(np.zeros(1)), bs.ctypes.data_as(_ip))
+    return bs[:nb + 1].copy()
+
+
+def eigvecs_split(d, e, il: int = 1, iu: int | None = None, orth: int = CWY_NEW,
+                  iters: int = 3, seed: int = DEFAULT_SEED):
+    """Eigenpairs il..iu of the matrix split into unreduced blocks; returns
+    (W, Z, nblocks, status, block of each column)."""
+    d, e = _f64(d), _f64(e)
+    n = len(d)
+    iu = n if iu is None else iu
+    m = iu - il + 1
+    L = lib()
+    L.or_eigvecs_split.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _dp, _dp,
+                                   ctypes.c_int, _ip, _ip]
+    L.or_eigvecs_split.restype = ctypes.c_int
+    W = np.empty(m)
+    Z = np.zeros((n, m), order="F")
+    st = np.zeros(m, dtype=np.int32)
+    blk = np.zeros(m, dtype=np.int32)
+    nb = L.or_eigvecs_split(n, _p(d), _p(e) if len(e) else _p(np.zeros(1)), il, iu, orth, iters,
+                            seed & (2**64 - 1), _p(W), _p(Z), n, st.ctypes.data_as(_ip),
+                            blk.ctypes.data_as(_ip))
+    if nb < 0:
+        raise ValueError(f"or_eigvecs_split failed: {nb}")
+    return W, Z, nb, st, blk

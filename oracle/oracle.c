@@ -636,3 +636,93 @@ int or_eigvecs(int n, const double *d, const double *e, int il, int iu, const do
     free(cst); free(csz); free(u1); free(swp); free(v); free(y); free(w); free(Y); free(T);
     return ncl;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Splitting into unreduced blocks.  The paper does not split; the LAPACK     */
+/* bisection and inverse-iteration codes its method builds on (section 4,     */
+/* section 5.1) work block by block.  Reading: e_i is negligible when         */
+/*     e_i^2 <= eps^2 |d_i d_{i+1}| + DBL_MIN,                                 */
+/* and T is then the direct sum of its unreduced blocks, each solved as an    */
+/* independent problem (its own norm, cluster gap and pivot floor).  The      */
+/* eigenvalues of all blocks, in ascending order with ties taken lower block  */
+/* first, are numbered 1..n; il..iu select from that order.  Eigenvalue l     */
+/* (0-based, ascending) of the block that starts at row s uses start-vector   */
+/* key s + 1 + l, rows numbered within the block; its eigenvector is the      */
+/* block's, zero outside the block.                                           */
+/* ------------------------------------------------------------------------- */
+
+/* Block starts: bstart[0] = 0 < bstart[1] < ... < bstart[nb] = n.  Returns nb. */
+int or_split_points(int n, const double *d, const double *e, int *bstart)
+{
+    int nb = 0;
+    bstart[nb++] = 0;
+    for (int i = 0; i < n - 1; i++) {
+        double lim = (DBL_EPSILON * DBL_EPSILON) * fabs(d[i] * d[i + 1]) + DBL_MIN;
+        if (e[i] * e[i] <= lim) bstart[nb++] = i + 1;
+    }
+    bstart[nb] = n;
+    return nb;
+}
+
+typedef struct { double v; int b, l; } or_bval;
+
+static int bval_cmp(const void *pa, const void *pb)
+{
+    const or_bval *a = (const or_bval *)pa, *b = (const or_bval *)pb;
+    if (a->v < b->v) return -1;
+    if (a->v > b->v) return 1;
+    if (a->b != b->b) return a->b < b->b ? -1 : 1;
+    return a->l < b->l ? -1 : (a->l > b->l);
+}
+
+/* As or_eigvecs (computed eigenvalues il..iu) on the split matrix.  blk (may
+ * be NULL, m entries) receives the block index of each output column.
+ * Returns the number of blocks, or < 0. */
+int or_eigvecs_split(int n, const double *d, const double *e, int il, int iu, int orth,
+                     int iters, uint64_t seed, double *W, double *Z, int ldz, int *status,
+                     int *blk)
+{
+    if (n < 1 || il < 1 || iu < il || iu > n || ldz < n) return -1;
+    int m = iu - il + 1;
+    int *bs = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    double *vals = (double *)malloc(sizeof(double) * (size_t)n);
+    or_bval *all = (or_bval *)malloc(sizeof(or_bval) * (size_t)n);
+    int *pos = (int *)malloc(sizeof(int) * (size_t)n);   /* output column of (block row s + l) */
+    if (!bs || !vals || !all || !pos) return -2;
+    int nb = or_split_points(n, d, e, bs);
+    for (int b = 0; b < nb; b++) {
+        int s = bs[b], nbk = bs[b + 1] - bs[b];
+        if (or_bisect(nbk, d + s, e + s, 1, nbk, vals + s)) return -2;
+        for (int l = 0; l < nbk; l++) { all[s + l].v = vals[s + l]; all[s + l].b = b; all[s + l].l = l; }
+    }
+    qsort(all, (size_t)n, sizeof(or_bval), bval_cmp);
+    for (int k = 0; k < n; k++) pos[bs[all[k].b] + all[k].l] = k - (il - 1);
+    for (int j = 0; j < m; j++)
+        for (int i = 0; i < n; i++) Z[i + (size_t)j * ldz] = 0.0;
+    for (int b = 0; b < nb; b++) {
+        int s = bs[b], nbk = bs[b + 1] - bs[b];
+        int lo = -1, hi = -2;                     /* selected local indices: a range */
+        for (int l = 0; l < nbk; l++) {
+            int p = pos[s + l];
+            if (p >= 0 && p < m) { if (lo < 0) lo = l; hi = l; }
+        }
+        if (lo < 0) continue;
+        int mb = hi - lo + 1;
+        double *Wb = (double *)malloc(sizeof(double) * (size_t)mb);
+        double *Zb = (double *)malloc(sizeof(double) * (size_t)nbk * mb);
+        int *stb = (int *)malloc(sizeof(int) * (size_t)mb);
+        if (!Wb || !Zb || !stb) return -2;
+        if (or_eigvecs(nbk, d + s, e + s, s + 1 + lo, s + 1 + hi, vals + s + lo, orth, iters,
+                       seed, Wb, Zb, nbk, stb) < 0) return -2;
+        for (int j = 0; j < mb; j++) {
+            int p = pos[s + lo + j];
+            W[p] = Wb[j];
+            for (int i = 0; i < nbk; i++) Z[(s + i) + (size_t)p * ldz] = Zb[i + (size_t)j * nbk];
+            if (status) status[p] = stb[j];
+            if (blk) blk[p] = b;
+        }
+        free(Wb); free(Zb); free(stb);
+    }
+    free(bs); free(vals); free(all); free(pos);
+    return nb;
+}

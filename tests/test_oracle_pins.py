@@ -460,3 +460,88 @@ def test_status_of_a_generic_problem():
     W2, Z2, _, st = O.eigvecs(d, e, with_status=True)
     assert np.array_equal(W, W2) and np.array_equal(Z, Z2)
     assert not (st & (O.ST_NONFINITE | O.ST_BREAKDOWN)).any()
+
+
+# --- splitting into unreduced blocks ----------------------------------------------------
+
+def _laplacian_blocks(sizes):
+    n = sum(sizes)
+    d = np.full(n, 2.0)
+    e = np.full(n - 1, -1.0)
+    s = 0
+    for b in sizes[:-1]:
+        s += b
+        e[s - 1] = 0.0
+    return d, e
+
+
+def test_split_laplacian_blocks_closed_form():
+    """Direct sum of tridiag(-1, 2, -1) blocks of sizes 5, 7 and 3: the
+    eigenvalues are the union of the blocks' closed forms (sizes 3 and 7
+    share 2 - 2 cos(pi/4), a double eigenvalue of T), and every vector is a
+    block's closed-form vector sin(i k pi / (n_b + 1)), exactly zero outside
+    its block, so even the double eigenvalue has block-supported vectors."""
+    sizes = [5, 7, 3]
+    d, e = _laplacian_blocks(sizes)
+    n = len(d)
+    assert list(O.split_points(d, e)) == [0, 5, 12, 15]
+    W, Z, nb, st, blk = O.eigvecs_split(d, e)
+    assert nb == 3
+    lam = np.sort(np.concatenate([2.0 - 2.0 * np.cos(np.arange(1, b + 1) * np.pi / (b + 1))
+                                  for b in sizes]))
+    assert np.max(np.abs(W - lam)) <= 8 * np.finfo(float).eps * 4.0
+    starts = [0, 5, 12]
+    seen = [0, 0, 0]
+    for j in range(n):
+        b = blk[j]
+        s, nbk = starts[b], sizes[b]
+        k = seen[b] + 1            # local eigenvalue index, ascending within the block
+        seen[b] += 1
+        z = Z[:, j]
+        assert np.all(z[:s] == 0.0) and np.all(z[s + nbk:] == 0.0)
+        ref = np.sqrt(2.0 / (nbk + 1)) * np.sin(np.arange(1, nbk + 1) * k * np.pi / (nbk + 1))
+        assert min(np.linalg.norm(z[s:s + nbk] - ref), np.linalg.norm(z[s:s + nbk] + ref)) <= 1e-12
+        assert abs(W[j] - (2.0 - 2.0 * np.cos(k * np.pi / (nbk + 1)))) <= 8 * np.finfo(float).eps * 4
+    assert not (st & (O.ST_NONFINITE | O.ST_BREAKDOWN)).any()
+
+
+def test_split_criterion_on_glued_wilkinson():
+    """Couplings of 1e-8 are not negligible next to diagonals of order 1 (no
+    split); couplings of 1e-20 and exact zeros split the matrix into its g
+    copies of W21+, whose eigenvalues then each appear g times, within the
+    coupling (Weyl) of the unsplit matrix's."""
+    g = 6
+    for delta, nb in ((1e-8, 1), (1e-20, g), (0.0, g)):
+        d, e = G.glued_wilkinson(g, delta)
+        assert len(O.split_points(d, e)) - 1 == nb, delta
+    d, e = G.glued_wilkinson(g, 1e-20)
+    W, Z, nb, _, blk = O.eigvecs_split(d, e)
+    assert nb == g
+    mu = np.sort(O.bisect(*G.glued_wilkinson(1, 0.0)))
+    assert np.max(np.abs(W - np.repeat(mu, g))) <= 1e-13
+    # each eigenvalue of W21+ has one vector per copy, supported on that copy
+    for j in range(len(W)):
+        b = blk[j]
+        z = Z[:, j]
+        assert np.linalg.norm(z[21 * b:21 * b + 21]) == pytest.approx(1.0, abs=1e-14)
+    assert orthogonality(Z) <= 1e-14
+    assert residual(d, e, W, Z) <= 1e-14
+
+
+def test_split_without_negligible_coupling_is_the_plain_method():
+    d, e = G.uniform_tridiag(150, 8)
+    W, Z, nb, st, blk = O.eigvecs_split(d, e)
+    W0, Z0, _, st0 = O.eigvecs(d, e, with_status=True)
+    assert nb == 1 and np.array_equal(W, W0) and np.array_equal(Z, Z0)
+    assert np.array_equal(st, st0) and not blk.any()
+
+
+def test_split_range_request():
+    """A range of the split spectrum: the same eigenvalues as that slice of
+    the full split request, residual and orthogonality at the bars."""
+    d, e = _laplacian_blocks([40, 25, 60])
+    W, Z, _, _, _ = O.eigvecs_split(d, e)
+    Wr, Zr, _, _, blk = O.eigvecs_split(d, e, 31, 90)
+    assert np.array_equal(Wr, W[30:90])
+    assert residual(d, e, Wr, Zr) <= 1e-13
+    assert orthogonality(Zr) <= 1e-13
