@@ -132,6 +132,27 @@ int tridiag_eigvecs_ex(const double *d, const double *e, int n, int il, int iu,
                        const te_opts *opt, void *ws, size_t ws_bytes, int *info,
                        hipStream_t stream);
 
+/* Eigenpairs il..iu of T split into unreduced blocks.  The paper does not
+ * split; the bisection and inverse-iteration codes its method builds on work
+ * block by block (section 4, section 5.1).  e_i is negligible when
+ * e_i^2 <= eps^2 |d_i d_{i+1}| + DBL_MIN; T is then the direct sum of its
+ * unreduced blocks and each block is an independent problem (its own norm,
+ * cluster gap and pivot floor), so clusters never span blocks.  The
+ * eigenvalues of all blocks in ascending order (ties: lower block first) are
+ * numbered 1..n and il..iu select from that order; W[j] and column j of Z are
+ * the j-th selected eigenpair, the vector exactly zero outside its block.
+ * Eigenvalue l (0-based, ascending) of the block that starts at row s uses
+ * start-vector key s + 1 + l (rows counted within the block); without a
+ * negligible e_i the result is that of tridiag_eigvecs_ex bit for bit.
+ * opt as for tridiag_eigvecs_ex (may be NULL).  info (device, may be NULL):
+ * 1 + m ints as for tridiag_eigvecs_ex.  nblocks (host, may be NULL)
+ * receives the number of blocks.  Allocates its workspace with
+ * hipMallocAsync on `stream` and synchronizes `stream` before returning.
+ * Argument positions: d=1 e=2 n=3 il=4 iu=5 W=6 Z=7 ldz=8 opt=9. */
+int tridiag_eigvecs_split(const double *d, const double *e, int n, int il, int iu, double *W,
+                          double *Z, int ldz, const te_opts *opt, int *info, int *nblocks,
+                          hipStream_t stream);
+
 /* ---- Entry point that allocates nothing ----
  * For callers that cannot allocate device memory while they run: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.

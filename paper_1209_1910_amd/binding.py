@@ -27,7 +27,7 @@ SYMBOLS = ("tridiag_eigvecs", "tridiag_eigvecs_given_w", "tridiag_eigvecs_worksp
            "te_batch_graph_create", "te_batch_graph_launch", "te_batch_graph_info",
            "te_batch_graph_destroy", "te_batch_autotune",
            "te_timing_enable", "te_timing_reset", "te_timing_read", "te_last_hip_error",
-           "tridiag_eigvecs_noalloc", "tridiag_eigvecs_noalloc_bytes")
+           "tridiag_eigvecs_noalloc", "tridiag_eigvecs_noalloc_bytes", "tridiag_eigvecs_split")
 PHASES = ("setup", "bisect", "clusters", "first_solves", "transpose", "chain_small",
           "chain_coop", "finalize")
 
@@ -70,6 +70,8 @@ def lib():
                                          ctypes.POINTER(te_opts), _vp, sz, _vp, _vp]
         L.tridiag_eigvecs_noalloc.argtypes = [_vp, _vp, i, i, i, _vp, _vp, _vp, i,
                                               ctypes.POINTER(te_opts), _vp, _vp]
+        L.tridiag_eigvecs_split.argtypes = [_vp, _vp, i, i, i, _vp, _vp, i,
+                                            ctypes.POINTER(te_opts), _vp, ip, _vp]
         L.tridiag_eigvecs_noalloc_bytes.argtypes = [i, i, i]
         L.tridiag_eigvecs_noalloc_bytes.restype = sz
         L.tridiag_eigvecs_batched.argtypes = [_vp, _vp, i64p, ip, ip, _vp, i64p, _vp, i64p, i,
@@ -264,6 +266,28 @@ def tridiag_eigvecs_ex(d, e, il=1, iu=None, W_given=None, ws=None, info=None, st
                                   _stream_ptr(stream))
     _check("tridiag_eigvecs_ex", rc)
     return W[:m], Z[:m], info
+
+
+def tridiag_eigvecs_split(d, e, il=1, iu=None, stream=None, device="cuda", **opts):
+    """Eigenpairs il..iu of tridiag(e, d, e) split into unreduced blocks.
+    Returns (W, Z, info, nblocks); row j of Z is the vector of W[j]."""
+    torch = _torch()
+    d = _dev_f64(d, device)
+    e = _dev_f64(e, device)
+    n = d.numel()
+    iu = n if iu is None else iu
+    m = iu - il + 1
+    W = torch.empty(max(m, 1), dtype=torch.float64, device=d.device)
+    Z = torch.empty((max(m, 1), n), dtype=torch.float64, device=d.device)
+    info = torch.zeros(m + 1, dtype=torch.int32, device=d.device)
+    nb = ctypes.c_int(0)
+    o = _opts(**opts)
+    rc = lib().tridiag_eigvecs_split(_vp(d.data_ptr()), _vp(e.data_ptr() if e.numel() else 0), n,
+                                     il, iu, _vp(W.data_ptr()), _vp(Z.data_ptr()), n,
+                                     ctypes.byref(o), _vp(info.data_ptr()), ctypes.byref(nb),
+                                     _stream_ptr(stream))
+    _check("tridiag_eigvecs_split", rc)
+    return W[:m], Z[:m], info, nb.value
 
 
 TE_NOALLOC_SCRATCH_BYTES = 256 << 20

@@ -488,7 +488,7 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
     carve_problem(cv, P, n, m);
     P.prm = cv.take<Params>(sizeof(Params));
     int *pinfo = cv.take<int>(sizeof(int) * ((size_t)m + 1));
-    P.info = (info && nprob == 1) ? info : pinfo;
+    P.info = pd[b].info ? pd[b].info : (info && nprob == 1) ? info : pinfo;
     std::memset(&hprm[b], 0, sizeof(Params));
     hprm[b].rtol = opt.rtol;
   }
@@ -1186,6 +1186,172 @@ int tridiag_eigvecs_noalloc(const double *d, const double *e, int n, int il, int
   std::vector<te::ProblemDesc> pd{{d, e, n, il, iu, W, Z, ldz}};
   return te::solve_problems(pd, W_given, te::resolve(opt), ws, TE_NOALLOC_SCRATCH_BYTES, info,
                             stream);
+}
+
+// ---- Splitting into unreduced blocks ----
+// Every block is an independent problem of the multi-problem path: first the
+// eigenvalues of every block (one bisection launch over all blocks), then,
+// on the host, the order of all eigenvalues (value, then block, then index
+// in the block) and the blocks' shares of il..iu, then the blocks' eigenpairs
+// from those eigenvalues (start-vector key s + 1 + l for eigenvalue l of the
+// block at row s), and last one scatter launch into the caller's columns.
+int tridiag_eigvecs_split(const double *d, const double *e, int n, int il, int iu, double *W,
+                          double *Z, int ldz, const te_opts *opt, int *info, int *nblocks,
+                          hipStream_t stream) {
+  if (!d) return -1;
+  if (!e && n > 1) return -2;
+  if (n < 1) return -3;
+  if (il < 1 || il > n) return -4;
+  if (iu < il || iu > n) return -5;
+  if (!W) return -6;
+  if (!Z) return -7;
+  if (ldz < n) return -8;
+  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return -9;
+  if (limits().device < 0) return TE_ERR_NO_DEVICE;
+  const int m = iu - il + 1;
+  OwnedBlocks owned(stream);
+  auto dalloc = [&](size_t bytes, void **p) -> int {
+    TE_CHECK(hipMallocAsync(p, std::max<size_t>(bytes, 256), stream));
+    owned.blocks.push_back(*p);
+    return 0;
+  };
+
+  // blocks
+  std::vector<int> bs{0};
+  {
+    SharedHold hold;
+    std::vector<unsigned char> hf((size_t)std::max(n - 1, 1), 0);
+    if (n > 1) {
+      unsigned char *df = nullptr;
+      if (int rc = dalloc((size_t)n, (void **)&df)) return rc;
+      TE_CHECK(launch_split_flags(d, e, n, df, stream));
+      TE_CHECK(hipMemcpyAsync(hf.data(), df, (size_t)(n - 1), hipMemcpyDeviceToHost, stream));
+      TE_CHECK(hipStreamSynchronize(stream));
+    }
+    for (int i = 0; i < n - 1; i++)
+      if (hf[i]) bs.push_back(i + 1);
+    bs.push_back(n);
+  }
+  const int nb = (int)bs.size() - 1;
+  if (nblocks) *nblocks = nb;
+
+  // eigenvalues of every block
+  std::vector<double> hw((size_t)n);
+  double *Wall = nullptr;
+  {
+    SharedHold hold;
+    size_t bytes = fixed_bytes(nb) + align_up(sizeof(double) * n);
+    for (int b = 0; b < nb; b++)
+      bytes += align_up(sizeof(double) * std::max(bs[b + 1] - bs[b] - 1, 1)) +
+               align_up(sizeof(Params));
+    char *base = nullptr;
+    if (int rc = dalloc(bytes, (void **)&base)) return rc;
+    Carve cv{base, 0, bytes};
+    Prob *dp = cv.take<Prob>(sizeof(Prob) * nb);
+    int64_t *dloff = cv.take<int64_t>(sizeof(int64_t) * (nb + 1));
+    Wall = cv.take<double>(sizeof(double) * n);
+    std::vector<Prob> hp((size_t)nb);
+    std::vector<Params> hprm((size_t)nb);
+    std::vector<int64_t> loff((size_t)nb + 1);
+    for (int b = 0; b < nb; b++) {
+      const int s0 = bs[b], nbk = bs[b + 1] - bs[b];
+      Prob &P = hp[b];
+      std::memset(&P, 0, sizeof(P));
+      P.d = d + s0;
+      P.e = e ? e + s0 : nullptr;
+      P.n = nbk; P.m = nbk; P.kbase = 1; P.W = Wall + s0; P.ldz = nbk;
+      P.e2 = cv.take<double>(sizeof(double) * std::max(nbk - 1, 1));
+      P.prm = cv.take<Params>(sizeof(Params));
+      std::memset(&hprm[b], 0, sizeof(Params));
+      hprm[b].rtol = 1e-3;
+      loff[b] = s0;
+    }
+    loff[nb] = n;
+    TE_CHECK(hipMemcpyAsync(dp, hp.data(), sizeof(Prob) * nb, hipMemcpyHostToDevice, stream));
+    TE_CHECK(hipMemcpyAsync(dloff, loff.data(), sizeof(int64_t) * (nb + 1),
+                            hipMemcpyHostToDevice, stream));
+    for (int b = 0; b < nb; b++)
+      TE_CHECK(hipMemcpyAsync(hp[b].prm, &hprm[b], sizeof(Params), hipMemcpyHostToDevice,
+                              stream));
+    TE_CHECK(launch_setup(dp, nb, stream));
+    TE_CHECK(launch_bisect(dp, nb, dloff, n, stream));
+    TE_CHECK(hipMemcpyAsync(hw.data(), Wall, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+    TE_CHECK(hipStreamSynchronize(stream));
+  }
+
+  // order of all eigenvalues; each block's share of il..iu is a contiguous range
+  std::vector<int> blk_of((size_t)n), ord((size_t)n), pos((size_t)n);
+  for (int b = 0; b < nb; b++)
+    for (int i = bs[b]; i < bs[b + 1]; i++) blk_of[i] = b;
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (hw[a] != hw[b]) return hw[a] < hw[b];
+    if (blk_of[a] != blk_of[b]) return blk_of[a] < blk_of[b];
+    return a < b;
+  });
+  for (int k = 0; k < n; k++) pos[ord[k]] = k - (il - 1);
+  struct Sel { int b, lo, hi; };
+  std::vector<Sel> sel;
+  size_t zsum = 0;
+  for (int b = 0; b < nb; b++) {
+    int lo = -1, hi = -2;
+    for (int i = bs[b]; i < bs[b + 1]; i++)
+      if (pos[i] >= 0 && pos[i] < m) { if (lo < 0) lo = i - bs[b]; hi = i - bs[b]; }
+    if (lo >= 0) {
+      sel.push_back({b, lo, hi});
+      zsum += (size_t)(bs[b + 1] - bs[b]) * (size_t)(hi - lo + 1);
+    }
+  }
+
+  // the selected blocks' eigenpairs from their eigenvalues
+  double *Wsel = nullptr, *Wt = nullptr, *Zt = nullptr;
+  int *It = nullptr;
+  SplitCol *dcols = nullptr;
+  if (int rc = dalloc(sizeof(double) * m, (void **)&Wsel)) return rc;
+  if (int rc = dalloc(sizeof(double) * m, (void **)&Wt)) return rc;
+  if (int rc = dalloc(sizeof(double) * zsum, (void **)&Zt)) return rc;
+  if (int rc = dalloc(sizeof(int) * ((size_t)m + sel.size()), (void **)&It)) return rc;
+  if (int rc = dalloc(sizeof(SplitCol) * m, (void **)&dcols)) return rc;
+  std::vector<ProblemDesc> pd;
+  std::vector<SplitCol> hc((size_t)m);
+  size_t woff = 0, zoff = 0, ioff = 0;
+  for (const Sel &q : sel) {
+    const int s0 = bs[q.b], nbk = bs[q.b + 1] - bs[q.b], mb = q.hi - q.lo + 1;
+    TE_CHECK(hipMemcpyAsync(Wsel + woff, Wall + s0 + q.lo, sizeof(double) * mb,
+                            hipMemcpyDeviceToDevice, stream));
+    ProblemDesc D{d + s0, e ? e + s0 : nullptr, nbk, s0 + 1 + q.lo, s0 + 1 + q.hi, Wt + woff,
+                  Zt + zoff, nbk, It + ioff};
+    pd.push_back(D);
+    for (int j = 0; j < mb; j++) {
+      SplitCol &c = hc[(size_t)pos[s0 + q.lo + j]];
+      c.src = Zt + zoff + (size_t)j * nbk;
+      c.w = Wt + woff + j;
+      c.st = It + ioff + 1 + j;
+      c.s = s0;
+      c.nb = nbk;
+      c.p = pos[s0 + q.lo + j];
+      c.pad = 0;
+    }
+    woff += (size_t)mb;
+    zoff += (size_t)nbk * mb;
+    ioff += (size_t)mb + 1;
+  }
+  const int rc = solve_problems(pd, Wsel, resolve(opt), nullptr, 0, nullptr, stream);
+  if (rc) return rc;
+
+  // into the caller's columns
+  {
+    SharedHold hold;
+    TE_CHECK(hipMemcpyAsync(dcols, hc.data(), sizeof(SplitCol) * m, hipMemcpyHostToDevice, stream));
+    if (info) TE_CHECK(launch_fill_i32(info, 1, 0, stream));
+    TE_CHECK(launch_split_scatter(dcols, m, n, W, Z, (size_t)ldz, info, stream));
+    TE_CHECK(hipStreamSynchronize(stream));
+  }
+  owned.released = true;
+  for (void *p : owned.blocks) TE_CHECK(hipFreeAsync(p, stream));
+  TE_CHECK(hipStreamSynchronize(stream));
+  return 0;
 }
 
 int tridiag_eigvals(const double *d, const double *e, int n, int il, int iu, double *W,

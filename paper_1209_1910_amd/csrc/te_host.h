@@ -40,6 +40,7 @@ struct ProblemDesc {
   int n, il, iu;
   double *W, *Z;
   int ldz;
+  int *info = nullptr;   // device, 1 + m ints; null: the workspace's own
 };
 
 // The whole method for a set of problems on `stream` (synchronizes it before

@@ -124,6 +124,19 @@ int mgs_max_wgs(int device);
 hipError_t launch_finalize(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
                            hipStream_t s);
 hipError_t launch_fill_i32(int *p, size_t n, int v, hipStream_t s);
+// Splitting into unreduced blocks.
+hipError_t launch_split_flags(const double *d, const double *e, int n, unsigned char *flag,
+                              hipStream_t s);
+struct SplitCol {
+  const double *src;   // the block's vector (nb entries)
+  const double *w;     // its eigenvalue
+  const int *st;       // its status word
+  int s, nb;           // block rows [s, s + nb)
+  int p;               // output column
+  int pad;
+};
+hipError_t launch_split_scatter(const SplitCol *cols, int m, int n, double *W, double *Z,
+                                size_t ldz, int *info, hipStream_t s);
 int coop_max_wgs(int device);
 int small_max_wgs(int device, int nt = 0);
 int device_cus(int device);

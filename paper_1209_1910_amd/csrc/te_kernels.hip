@@ -2193,6 +2193,57 @@ hipError_t launch_finalize(const Prob *probs, int nprob, const int64_t *loff, in
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Splitting into unreduced blocks: flag[i] = 1 when e_i is negligible,
+// e_i^2 <= eps^2 |d_i d_{i+1}| + DBL_MIN (each operation rounded on its own).
+// ---------------------------------------------------------------------------
+
+__global__ void k_split_flags(const double *__restrict__ d, const double *__restrict__ e, int n,
+                              unsigned char *__restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const double lim = (DBL_EPSILON * DBL_EPSILON) * fabs(d[i] * d[i + 1]) + DBL_MIN;
+  flag[i] = (e[i] * e[i] <= lim) ? 1 : 0;
+}
+
+hipError_t launch_split_flags(const double *d, const double *e, int n, unsigned char *flag,
+                              hipStream_t s) {
+  if (n < 2) return hipSuccess;
+  hipLaunchKernelGGL(k_split_flags, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s, d, e,
+                     n, flag);
+  return hipGetLastError();
+}
+
+// Block results -> the caller's columns: column p of Z (leading dimension
+// ldz, n rows) is zero outside rows [s, s + nb) and holds the block's vector
+// (src, nb entries) inside; W[p] and the status word follow.  One 256-thread
+// workgroup per column.
+__global__ void __launch_bounds__(256) k_split_scatter(const SplitCol *__restrict__ cols, int n,
+                                                       double *__restrict__ W,
+                                                       double *__restrict__ Z, size_t ldz,
+                                                       int *__restrict__ info) {
+  const SplitCol c = cols[blockIdx.x];
+  double *z = Z + (size_t)c.p * ldz;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    z[i] = (i >= c.s && i < c.s + c.nb) ? c.src[i - c.s] : 0.0;
+  if (threadIdx.x == 0) {
+    W[c.p] = *c.w;
+    if (info) {
+      const int st = *c.st;
+      info[1 + c.p] = st;
+      if (st) atomicAdd(info, 1);
+    }
+  }
+}
+
+hipError_t launch_split_scatter(const SplitCol *cols, int m, int n, double *W, double *Z,
+                                size_t ldz, int *info, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_scatter, dim3((unsigned)m), dim3(256), 0, s, cols, n, W, Z, ldz,
+                     info);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_i32(int *p, size_t n, int v) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
