@@ -251,3 +251,28 @@ def eigvecs_split(d, e, il: int = 1, iu: int | None = None, orth: int = CWY_NEW,
     if nb < 0:
         raise ValueError(f"or_eigvecs_split failed: {nb}")
     return W, Z, nb, st, blk
+
+
+def bidiag_svd(a, b, il: int = 1, iu: int | None = None, orth: int = CWY_NEW, iters: int = 3,
+               seed: int = DEFAULT_SEED):
+    """Singular values (ascending) il..iu of the upper bidiagonal matrix with
+    diagonal a and superdiagonal b, and their left (U) and right (V) singular
+    vectors as columns; returns (S, U, V, status)."""
+    a, b = _f64(a), _f64(b)
+    n = len(a)
+    iu = n if iu is None else iu
+    m = iu - il + 1
+    L = lib()
+    L.or_bidiag_svd.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _dp, _dp,
+                                ctypes.c_int, _dp, ctypes.c_int, _ip]
+    L.or_bidiag_svd.restype = ctypes.c_int
+    S = np.empty(m)
+    U = np.zeros((n, m), order="F")
+    V = np.zeros((n, m), order="F")
+    st = np.zeros(m, dtype=np.int32)
+    rc = L.or_bidiag_svd(n, _p(a), _p(b) if len(b) else _p(np.zeros(1)), il, iu, orth, iters,
+                         seed & (2**64 - 1), _p(S), _p(U), n, _p(V), n, st.ctypes.data_as(_ip))
+    if rc < 0:
+        raise ValueError(f"or_bidiag_svd failed: {rc}")
+    return S, U, V, st

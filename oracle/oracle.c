@@ -726,3 +726,46 @@ int or_eigvecs_split(int n, const double *d, const double *e, int il, int iu, in
     free(bs); free(vals); free(all); free(pos);
     return nb;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Singular vectors of a bidiagonal matrix, the application the paper names   */
+/* as future work (section 6), through the Golub-Kahan tridiagonal: for upper */
+/* bidiagonal B (diagonal a[0..n-1], superdiagonal b[0..n-2]), the symmetric  */
+/* tridiagonal of order 2n with zero diagonal and off-diagonal                */
+/* (a_0, b_0, a_1, b_1, ..., b_{n-2}, a_{n-1}) has eigenvalues +-sigma_i, and */
+/* an eigenvector (x_0, y_0, x_1, y_1, ...) of +sigma gives B x = sigma y and */
+/* B^T y = sigma x.  Singular values in ascending order, indices il..iu of    */
+/* 1..n, are the tridiagonal's eigenvalues n + il .. n + iu (the method with  */
+/* its clusters formed among those, start-vector keys n + il + j); V takes    */
+/* the x half and U the y half of each vector, each normalized to unit        */
+/* 2-norm (reading: the halves are normalized separately).                    */
+/* ------------------------------------------------------------------------- */
+
+int or_bidiag_svd(int n, const double *a, const double *b, int il, int iu, int orth, int iters,
+                  uint64_t seed, double *S, double *U, int ldu, double *V, int ldv, int *status)
+{
+    if (n < 1 || il < 1 || iu < il || iu > n || ldu < n || ldv < n) return -1;
+    int N = 2 * n, m = iu - il + 1;
+    double *dg = (double *)calloc((size_t)N, sizeof(double));
+    double *eg = (double *)malloc(sizeof(double) * (size_t)(N - 1));
+    double *Zg = (double *)malloc(sizeof(double) * (size_t)N * m);
+    if (!dg || !eg || !Zg) return -2;
+    for (int k = 0; k < n; k++) {
+        eg[2 * k] = a[k];
+        if (k < n - 1) eg[2 * k + 1] = b[k];
+    }
+    int ncl = or_eigvecs(N, dg, eg, n + il, n + iu, NULL, orth, iters, seed, S, Zg, N, status);
+    if (ncl < 0) return ncl;
+    for (int j = 0; j < m; j++) {
+        const double *z = Zg + (size_t)j * N;
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k < n; k++) { sx = sx + z[2 * k] * z[2 * k]; sy = sy + z[2 * k + 1] * z[2 * k + 1]; }
+        double nx = sqrt(sx), ny = sqrt(sy);
+        for (int k = 0; k < n; k++) {
+            V[k + (size_t)j * ldv] = z[2 * k] / nx;
+            U[k + (size_t)j * ldu] = z[2 * k + 1] / ny;
+        }
+    }
+    free(dg); free(eg); free(Zg);
+    return ncl;
+}

@@ -545,3 +545,62 @@ def test_split_range_request():
     assert np.array_equal(Wr, W[30:90])
     assert residual(d, e, Wr, Zr) <= 1e-13
     assert orthogonality(Zr) <= 1e-13
+
+
+# --- singular vectors of a bidiagonal matrix (Golub-Kahan tridiagonal) --------------------
+
+def _bidiag(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(2.0, 3.0, n), rng.uniform(-1.0, 1.0, n - 1)
+
+
+def test_bidiag_all_ones_closed_form():
+    """The upper bidiagonal matrix of ones has singular values
+    2 cos(k pi / (2n + 1)); its Golub-Kahan tridiagonal is tridiag(1, 0, 1)
+    of order 2n, whose eigenvectors sin(i j pi / (2n + 1)) interleave the
+    right (odd rows) and left (even rows) singular vectors."""
+    n = 40
+    a, b = np.ones(n), np.ones(n - 1)
+    S, U, V, st = O.bidiag_svd(a, b)
+    k = np.arange(n, 0, -1)                        # ascending singular values
+    assert np.max(np.abs(S - 2.0 * np.cos(k * np.pi / (2 * n + 1)))) <= 8 * np.finfo(float).eps * 2
+    N = 2 * n
+    i = np.arange(1, N + 1)
+    for col, kk in enumerate(k):
+        # eigenvector of 2 cos(kk pi / (N + 1)) = +sigma_k of tridiag(1, 0, 1); the
+        # vector of -sigma_k, sin(i (N + 1 - kk) pi / (N + 1)), has the same x half and
+        # the opposite y half
+        z = np.sin(i * kk * np.pi / (N + 1))
+        v, u = z[0::2] / np.linalg.norm(z[0::2]), z[1::2] / np.linalg.norm(z[1::2])
+        sv = np.sign(v @ V[:, col])
+        assert np.linalg.norm(V[:, col] - sv * v) <= 1e-9
+        assert np.linalg.norm(U[:, col] - sv * u) <= 1e-9
+    assert not (st & (O.ST_NONFINITE | O.ST_BREAKDOWN)).any()
+
+
+def test_bidiag_svd_against_lapack_and_identities():
+    """Singular values against LAPACK's SVD of the dense matrix (a library
+    cross-check), vectors against its singular vectors (distinct values),
+    and B V = U S, B^T U = V S, orthonormal U and V."""
+    n = 120
+    a, b = _bidiag(n, 5)
+    Bm = np.diag(a) + np.diag(b, 1)
+    S, U, V, _ = O.bidiag_svd(a, b)
+    Ul, Sl, Vlt = np.linalg.svd(Bm)
+    order = np.argsort(Sl)
+    assert np.max(np.abs(S - Sl[order])) <= 16 * np.finfo(float).eps * np.max(Sl)
+    assert np.max(sin_angles(U, Ul[:, order])) <= 1e-9
+    assert np.max(sin_angles(V, Vlt.T[:, order])) <= 1e-9
+    assert np.max(np.abs(Bm @ V - U * S)) <= 1e-13 * np.max(Sl)
+    assert np.max(np.abs(Bm.T @ U - V * S)) <= 1e-13 * np.max(Sl)
+    assert orthogonality(U) <= 1e-13 and orthogonality(V) <= 1e-13
+
+
+def test_bidiag_svd_range():
+    n = 90
+    a, b = _bidiag(n, 6)
+    S, U, V, _ = O.bidiag_svd(a, b)
+    Sr, Ur, Vr, _ = O.bidiag_svd(a, b, 11, 40)
+    assert np.array_equal(Sr, S[10:40])
+    Bm = np.diag(a) + np.diag(b, 1)
+    assert np.max(np.abs(Bm @ Vr - Ur * Sr)) <= 1e-13 * 4.0
