@@ -153,6 +153,27 @@ int tridiag_eigvecs_split(const double *d, const double *e, int n, int il, int i
                           double *Z, int ldz, const te_opts *opt, int *info, int *nblocks,
                           hipStream_t stream);
 
+/* Singular values and vectors of an upper bidiagonal matrix B (diagonal a[0..n-1],
+ * superdiagonal b[0..n-2], device arrays), the application the paper names
+ * for its method (section 6).  B's Golub-Kahan tridiagonal of order 2n (zero
+ * diagonal, off-diagonal a_0, b_0, a_1, ..., b_{n-2}, a_{n-1}) has eigenvalues
+ * +-sigma_i, and an eigenvector (x_0, y_0, x_1, y_1, ...) of +sigma gives
+ * B x = sigma y, B^T y = sigma x.  The singular values in ascending order,
+ * indices il..iu of 1..n, are that tridiagonal's eigenvalues n + il .. n + iu,
+ * computed with the same method (bisection, clusters among the requested
+ * ones, inverse iteration with compact-WY re-orthogonalization, start-vector
+ * keys n + il + j).  S[j] receives sigma, column j of V (ld ldv) the x half and
+ * column j of U (ld ldu) the y half of its vector, each normalized to unit
+ * 2-norm.  A singular value below half the cluster gap (1e-3 of the
+ * tridiagonal's 1-norm) shares a cluster with its negative, which is not
+ * requested: the two halves are then normalized separately, which keeps their
+ * directions.  info (device, may be
+ * NULL): 1 + m status ints as for tridiag_eigvecs_ex.  Allocates its
+ * workspace with hipMallocAsync and synchronizes `stream` before returning.
+ * Argument positions: a=1 b=2 n=3 il=4 iu=5 S=6 U=7 ldu=8 V=9 ldv=10 opt=11. */
+int bidiag_svd(const double *a, const double *b, int n, int il, int iu, double *S, double *U,
+               int ldu, double *V, int ldv, const te_opts *opt, int *info, hipStream_t stream);
+
 /* ---- Entry point that allocates nothing ----
  * For callers that cannot allocate device memory while they run: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.

@@ -27,7 +27,7 @@ SYMBOLS = ("tridiag_eigvecs", "tridiag_eigvecs_given_w", "tridiag_eigvecs_worksp
            "te_batch_graph_create", "te_batch_graph_launch", "te_batch_graph_info",
            "te_batch_graph_destroy", "te_batch_autotune",
            "te_timing_enable", "te_timing_reset", "te_timing_read", "te_last_hip_error",
-           "tridiag_eigvecs_noalloc", "tridiag_eigvecs_noalloc_bytes", "tridiag_eigvecs_split")
+           "tridiag_eigvecs_noalloc", "tridiag_eigvecs_noalloc_bytes", "tridiag_eigvecs_split", "bidiag_svd")
 PHASES = ("setup", "bisect", "clusters", "first_solves", "transpose", "chain_small",
           "chain_coop", "finalize")
 
@@ -72,6 +72,8 @@ def lib():
                                               ctypes.POINTER(te_opts), _vp, _vp]
         L.tridiag_eigvecs_split.argtypes = [_vp, _vp, i, i, i, _vp, _vp, i,
                                             ctypes.POINTER(te_opts), _vp, ip, _vp]
+        L.bidiag_svd.argtypes = [_vp, _vp, i, i, i, _vp, _vp, i, _vp, i, ctypes.POINTER(te_opts),
+                                 _vp, _vp]
         L.tridiag_eigvecs_noalloc_bytes.argtypes = [i, i, i]
         L.tridiag_eigvecs_noalloc_bytes.restype = sz
         L.tridiag_eigvecs_batched.argtypes = [_vp, _vp, i64p, ip, ip, _vp, i64p, _vp, i64p, i,
@@ -288,6 +290,28 @@ def tridiag_eigvecs_split(d, e, il=1, iu=None, stream=None, device="cuda", **opt
                                      _stream_ptr(stream))
     _check("tridiag_eigvecs_split", rc)
     return W[:m], Z[:m], info, nb.value
+
+
+def bidiag_svd(a, b, il=1, iu=None, stream=None, device="cuda", **opts):
+    """Singular values (ascending) il..iu of the upper bidiagonal matrix with
+    diagonal a and superdiagonal b, with left and right singular vectors.
+    Returns (S, U, V, info): row j of U and of V is the pair of S[j]."""
+    torch = _torch()
+    a = _dev_f64(a, device)
+    b = _dev_f64(b, device)
+    n = a.numel()
+    iu = n if iu is None else iu
+    m = iu - il + 1
+    S = torch.empty(max(m, 1), dtype=torch.float64, device=a.device)
+    U = torch.empty((max(m, 1), n), dtype=torch.float64, device=a.device)
+    V = torch.empty((max(m, 1), n), dtype=torch.float64, device=a.device)
+    info = torch.zeros(m + 1, dtype=torch.int32, device=a.device)
+    o = _opts(**opts)
+    rc = lib().bidiag_svd(_vp(a.data_ptr()), _vp(b.data_ptr() if b.numel() else 0), n, il, iu,
+                          _vp(S.data_ptr()), _vp(U.data_ptr()), n, _vp(V.data_ptr()), n,
+                          ctypes.byref(o), _vp(info.data_ptr()), _stream_ptr(stream))
+    _check("bidiag_svd", rc)
+    return S[:m], U[:m], V[:m], info
 
 
 TE_NOALLOC_SCRATCH_BYTES = 256 << 20

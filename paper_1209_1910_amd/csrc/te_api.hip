@@ -1354,6 +1354,49 @@ int tridiag_eigvecs_split(const double *d, const double *e, int n, int il, int i
   return 0;
 }
 
+int bidiag_svd(const double *a, const double *b, int n, int il, int iu, double *S, double *U,
+               int ldu, double *V, int ldv, const te_opts *opt, int *info, hipStream_t stream) {
+  if (!a) return -1;
+  if (!b && n > 1) return -2;
+  if (n < 1 || n > (1 << 30)) return -3;
+  if (il < 1 || il > n) return -4;
+  if (iu < il || iu > n) return -5;
+  if (!S) return -6;
+  if (!U) return -7;
+  if (ldu < n) return -8;
+  if (!V) return -9;
+  if (ldv < n) return -10;
+  if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return -11;
+  if (limits().device < 0) return TE_ERR_NO_DEVICE;
+  const int N = 2 * n, m = iu - il + 1;
+  OwnedBlocks owned(stream);
+  double *dg = nullptr, *eg = nullptr, *Zg = nullptr;
+  for (auto pr : {std::make_pair((void **)&dg, sizeof(double) * N),
+                  std::make_pair((void **)&eg, sizeof(double) * N),
+                  std::make_pair((void **)&Zg, sizeof(double) * (size_t)N * m)}) {
+    TE_CHECK(hipMallocAsync(pr.first, pr.second, stream));
+    owned.blocks.push_back(*pr.first);
+  }
+  {
+    SharedHold hold;
+    TE_CHECK(launch_gk_build(a, b, n, dg, eg, stream));
+  }
+  // +sigma_il .. +sigma_iu are the tridiagonal's eigenvalues n + il .. n + iu
+  std::vector<ProblemDesc> pd{{dg, eg, N, n + il, n + iu, S, Zg, N, info}};
+  const int rc = solve_problems(pd, nullptr, resolve(opt), nullptr, 0, nullptr, stream);
+  if (rc) return rc;
+  {
+    SharedHold hold;
+    TE_CHECK(launch_gk_split(Zg, n, m, U, (size_t)ldu, V, (size_t)ldv, stream));
+    TE_CHECK(hipStreamSynchronize(stream));
+  }
+  owned.released = true;
+  for (void *p : owned.blocks) TE_CHECK(hipFreeAsync(p, stream));
+  TE_CHECK(hipStreamSynchronize(stream));
+  return 0;
+}
+
 int tridiag_eigvals(const double *d, const double *e, int n, int il, int iu, double *W,
                     hipStream_t stream) {
   if (!d) return -1;

@@ -135,6 +135,11 @@ struct SplitCol {
   int p;               // output column
   int pad;
 };
+// Bidiagonal singular vectors through the Golub-Kahan tridiagonal.
+hipError_t launch_gk_build(const double *a, const double *b, int n, double *dg, double *eg,
+                           hipStream_t s);
+hipError_t launch_gk_split(const double *Zg, int n, int m, double *U, size_t ldu, double *V,
+                           size_t ldv, hipStream_t s);
 hipError_t launch_split_scatter(const SplitCol *cols, int m, int n, double *W, double *Z,
                                 size_t ldz, int *info, hipStream_t s);
 int coop_max_wgs(int device);

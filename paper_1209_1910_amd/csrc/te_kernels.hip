@@ -2244,6 +2244,69 @@ hipError_t launch_split_scatter(const SplitCol *cols, int m, int n, double *W, d
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Singular vectors of an upper bidiagonal B (diagonal a, superdiagonal b)
+// through its Golub-Kahan tridiagonal of order 2n: zero diagonal, off-diagonal
+// (a_0, b_0, a_1, ..., b_{n-2}, a_{n-1}).  An eigenvector (x_0, y_0, x_1, ...)
+// of +sigma gives the right (x) and left (y) singular vectors.
+// ---------------------------------------------------------------------------
+
+__global__ void k_gk_build(const double *__restrict__ a, const double *__restrict__ b, int n,
+                           double *__restrict__ dg, double *__restrict__ eg) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * n) return;
+  dg[t] = 0.0;
+  if (t < 2 * n - 1) eg[t] = (t & 1) ? b[t >> 1] : a[t >> 1];
+}
+
+hipError_t launch_gk_build(const double *a, const double *b, int n, double *dg, double *eg,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_gk_build, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, s, a, b, n,
+                     dg, eg);
+  return hipGetLastError();
+}
+
+// Column j of Zg (2n entries): V column = even entries, U column = odd
+// entries, each scaled to unit 2-norm.  One 256-thread workgroup per column;
+// the sums of squares in a fixed order (per-thread strided partial sums, then
+// the workgroup tree), so the result does not depend on timing.
+__global__ void __launch_bounds__(256) k_gk_split(const double *__restrict__ Zg, int n,
+                                                  double *__restrict__ U, size_t ldu,
+                                                  double *__restrict__ V, size_t ldv) {
+  __shared__ double sx[256], sy[256];
+  const double *z = Zg + (size_t)blockIdx.x * (size_t)(2 * n);
+  double px = 0.0, py = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) {
+    const double x = z[2 * k], y = z[2 * k + 1];
+    px = fma(x, x, px);
+    py = fma(y, y, py);
+  }
+  sx[threadIdx.x] = px;
+  sy[threadIdx.x] = py;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sx[threadIdx.x] = sx[threadIdx.x] + sx[threadIdx.x + w];
+      sy[threadIdx.x] = sy[threadIdx.x] + sy[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  const double rx = 1.0 / sqrt(sx[0]), ry = 1.0 / sqrt(sy[0]);
+  double *u = U + (size_t)blockIdx.x * ldu;
+  double *v = V + (size_t)blockIdx.x * ldv;
+  for (int k = threadIdx.x; k < n; k += 256) {
+    v[k] = z[2 * k] * rx;
+    u[k] = z[2 * k + 1] * ry;
+  }
+}
+
+hipError_t launch_gk_split(const double *Zg, int n, int m, double *U, size_t ldu, double *V,
+                           size_t ldv, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gk_split, dim3((unsigned)m), dim3(256), 0, s, Zg, n, U, ldu, V, ldv);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_i32(int *p, size_t n, int v) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

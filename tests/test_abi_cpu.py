@@ -76,6 +76,9 @@ def test_other_entry_points_argument_errors():
     assert L.tridiag_eigvecs_noalloc(P, P, 10, 1, 10, NULL, P, P, 10, ctypes.byref(o), NULL,
                                      NULL) == -10
     assert L.tridiag_eigvecs_noalloc_bytes(10, 4, 3) == 0
+    assert L.bidiag_svd(NULL, P, 10, 1, 10, P, P, 10, P, 10, None, NULL, NULL) == -1
+    assert L.bidiag_svd(P, P, 10, 1, 11, P, P, 10, P, 10, None, NULL, NULL) == -5
+    assert L.bidiag_svd(P, P, 10, 1, 10, P, P, 10, P, 9, None, NULL, NULL) == -10
     assert L.tridiag_eigvecs_split(NULL, P, 10, 1, 10, P, P, 10, None, NULL, None, NULL) == -1
     assert L.tridiag_eigvecs_split(P, P, 10, 2, 1, P, P, 10, None, NULL, None, NULL) == -5
     assert L.tridiag_eigvecs_split(P, P, 10, 1, 10, P, P, 9, None, NULL, None, NULL) == -8
