@@ -26,7 +26,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 CWY_NEW, CWY_ORDINARY, HOUSEHOLDER, MGS = 0, 1, 2, 3
 # per-vector status bits of eigvecs(..., with_status=True)
-ST_NONFINITE, ST_BREAKDOWN, ST_PIVOT = 1, 2, 4
+ST_NONFINITE, ST_BREAKDOWN, ST_PIVOT, ST_NOCONV = 1, 2, 4, 8
+# iters = STOP_GROWTH selects the growth stop rule instead of a fixed count
+STOP_GROWTH = -1
 DEFAULT_SEED = 0x1209_1910
 
 _dp = ctypes.POINTER(ctypes.c_double)

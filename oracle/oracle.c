@@ -472,10 +472,29 @@ static int orth_householder(int n, int c, double *Y, int ldy, double *T, int ldt
 
 enum { OR_CWY_NEW = 0, OR_CWY_ORDINARY = 1, OR_HOUSEHOLDER = 2, OR_MGS = 3 };
 
+/* The stop test of the repeat loop (Alg. 1 and Alg. 4 repeat "until some
+ * condition is met" and leave the condition open).  Default reading: a fixed
+ * number of iterations.  The growth rule (iters = OR_STOP_GROWTH), in the
+ * manner of the inverse-iteration code the paper starts from: a solve
+ * (T - lambda I) x = v with ||v||_2 = 1 has converged when its growth is large,
+ * ||x||_2 >= 1 / (n eps ||T||_1) -- 1/||x||_2 is the residual of x/||x||_2 --
+ * with ||x||_2^2 summed from the last row up with fused multiply-adds; after
+ * the first converged solve the vector gets OR_STOP_EXTRA more iterations, at
+ * most OR_STOP_MAXITS in all. */
+enum { OR_STOP_GROWTH = -1, OR_STOP_EXTRA = 2, OR_STOP_MAXITS = 5 };
+
+static int or_solve_converged(int n, const double *x, double gtau)
+{
+    double ss = 0.0;
+    for (int i = n - 1; i >= 0; i--) ss = fma(x[i], x[i], ss);
+    return sqrt(ss) * gtau >= 1.0;
+}
+
 /* Per-vector status bits of or_eigvecs: a non-finite entry in the output; a
  * reflector of one of its orthogonalizations broke down (||u_hat|| = 0, so
- * H = I); a pivot of its shifted LU fell below eps ||T||_1 and was replaced. */
-enum { OR_ST_NONFINITE = 1, OR_ST_BREAKDOWN = 2, OR_ST_PIVOT = 4 };
+ * H = I); a pivot of its shifted LU fell below eps ||T||_1 and was replaced;
+ * under the growth rule, no solve of the vector converged. */
+enum { OR_ST_NONFINITE = 1, OR_ST_BREAKDOWN = 2, OR_ST_PIVOT = 4, OR_ST_NOCONV = 8 };
 
 /* Householder vector and t of the first vector of a sequence (Alg. 3 line 1). */
 static void orth_first(int n, int variant, double *Y, int ldy, double *T, int ldt,
@@ -555,7 +574,8 @@ int or_orthogonalize(int n, int m, const double *V, int ldv, double *Q, int ldq,
  * il is only the base of the start-vector key (eigenvalue j uses key index
  * il + j).  orth: 0 new cWY (Alg. 4 with section 3.3.2), 1 ordinary cWY,
  * 2 Householder, 3 MGS (Alg. 1).  iters: fixed iteration count (the paper
- * leaves the stop test of the repeat loop open; it is read as a fixed count).  Each output
+ * leaves the stop test of the repeat loop open; it is read as a fixed count),
+ * or OR_STOP_GROWTH for the growth rule above.  Each output
  * column is normalized to unit 2-norm and its largest-magnitude entry (lowest
  * index on ties) made positive.  status (may be NULL, m entries) receives the
  * OR_ST_* bits of each vector.  Returns the number of clusters, or < 0. */
@@ -581,6 +601,7 @@ int or_eigvecs(int n, const double *d, const double *e, int il, int iu, const do
     if (!cst || !csz || !u1 || !swp || !v || !y || !w) return -2;
     double *u2 = u1 + n, *u3 = u1 + 2 * (size_t)n, *lm = u1 + 3 * (size_t)n;
     int ncl = or_clusters(m, W, p.tol, cst, csz);
+    double gtau = ((double)n * DBL_EPSILON) * p.norm1;   /* growth rule threshold */
 
     int maxsz = 1;
     for (int c = 0; c < ncl; c++) if (csz[c] > maxsz) maxsz = csz[c];
@@ -595,10 +616,16 @@ int or_eigvecs(int n, const double *d, const double *e, int il, int iu, const do
             int st = 0;
             if (or_lu(n, d, e, W[j], p.pivthr, u1, u2, u3, lm, swp) > 0) st |= OR_ST_PIVOT;
             or_start_vector(seed, (int64_t)il + j, n, v);
-            for (int k = 1; k <= iters; k++) {
+            int kend = iters > 0 ? iters : OR_STOP_MAXITS;
+            int conv = 0;
+            for (int k = 1; k <= kend; k++) {
                 double nv = nrm2(n, v);          /* normalize v^(k-1) */
                 for (int i = 0; i < n; i++) v[i] = v[i] / nv;
                 or_lu_solve(n, u1, u2, u3, lm, swp, v, y);   /* Eq. (1) */
+                if (iters < 0 && !conv && or_solve_converged(n, v, gtau)) {
+                    conv = 1;
+                    if (k + OR_STOP_EXTRA < kend) kend = k + OR_STOP_EXTRA;
+                }
                 if (jc == 0) continue;
                 if (orth == OR_MGS) {            /* Alg. 1: MGS against v_{j1}..v_{j-1} */
                     for (int r = j1; r < j; r++) {
@@ -617,6 +644,7 @@ int or_eigvecs(int n, const double *d, const double *e, int il, int iu, const do
                 else b = orth_householder(n, jc, Y, n, T, maxsz, v, w);
                 if (b) st |= OR_ST_BREAKDOWN;
             }
+            if (iters < 0 && !conv) st |= OR_ST_NOCONV;
             double nv = nrm2(n, v);              /* normalize v^(k) to v_j */
             double *z = Z + (size_t)j * ldz;
             for (int i = 0; i < n; i++) z[i] = v[i] / nv;

@@ -604,3 +604,65 @@ def test_bidiag_svd_range():
     assert np.array_equal(Sr, S[10:40])
     Bm = np.diag(a) + np.diag(b, 1)
     assert np.max(np.abs(Bm @ Vr - Ur * Sr)) <= 1e-13 * 4.0
+
+
+# --- the growth stop rule ---------------------------------------------------------------
+
+def _first_solve_ratio(d, e, W, j, kglob, solves):
+    """1/||x|| / (n eps ||T||_1) after `solves` normalized solves from the
+    start vector, recomputed here with the oracle's LU (a ratio <= 1 means
+    converged by the growth rule)."""
+    n = len(d)
+    p = O.setup(d, e)
+    f = O.lu(d, e, W[j], p.pivthr)
+    v = O.start_vector(O.DEFAULT_SEED, kglob, n)
+    for _ in range(solves):
+        v = O.lu_solve(f, v / np.linalg.norm(v))
+    return 1.0 / np.linalg.norm(v) / (n * np.finfo(float).eps * p.norm1)
+
+
+def test_growth_rule_extra_iterations_on_singletons():
+    """Vectors that are not re-orthogonalized (singletons and first cluster
+    members) converged at the first solve get two more iterations (the
+    fixed-3 result), those converged only at the second get two more after
+    it (the fixed-4 result); none of the n = 1000 workload's vectors hits
+    the cap."""
+    d, e = G.workload_small()
+    W, Z3, _ = O.eigvecs(d, e, iters=3)
+    _, Z4, _ = O.eigvecs(d, e, iters=4)
+    Wg, Zg, _, st = O.eigvecs(d, e, iters=O.STOP_GROWTH, with_status=True)
+    assert np.array_equal(W, Wg)
+    assert not (st & O.ST_NOCONV).any()
+    st_, sz_ = O.clusters(W, O.setup(d, e).tol)
+    singles = [int(s) for s in st_]
+    n3 = n4 = 0
+    for j in singles:
+        r1 = _first_solve_ratio(d, e, W, j, j + 1, 1)
+        if r1 <= 0.5:
+            assert np.array_equal(Zg[:, j], Z3[:, j]), j
+            n3 += 1
+        elif r1 > 2.0 and _first_solve_ratio(d, e, W, j, j + 1, 2) <= 0.5:
+            assert np.array_equal(Zg[:, j], Z4[:, j]), j
+            n4 += 1
+    assert n3 > 100 and n4 >= 1, (n3, n4)
+
+
+@pytest.mark.parametrize("orth", [O.CWY_NEW, O.MGS])
+def test_growth_rule_cap_with_inaccurate_shifts(orth):
+    """Shifts 1e-6 away from the eigenvalues bound the growth by about 1e6,
+    far below 1 / (n eps ||T||_1): no solve converges, every vector runs the
+    cap of 5 iterations (the fixed-5 result) and carries the flag."""
+    d, e = G.uniform_tridiag(200, 4)
+    W = O.bisect(d, e) + 1e-6
+    _, Z5, _ = O.eigvecs(d, e, W=W, iters=5, orth=orth)
+    _, Zg, _, st = O.eigvecs(d, e, W=W, iters=O.STOP_GROWTH, orth=orth, with_status=True)
+    assert np.array_equal(Z5, Zg)
+    assert np.all(st & O.ST_NOCONV)
+
+
+def test_growth_rule_accuracy():
+    """Under the growth rule the method keeps the accuracy bars."""
+    for d, e in (G.workload_small(), G.glued_wilkinson(24, 1e-8), G.laplacian_tridiag(500)):
+        W, Z, _ = O.eigvecs(d, e, iters=O.STOP_GROWTH)
+        assert residual(d, e, W, Z) <= 1e-12
+        assert orthogonality(Z) <= 1e-11
