@@ -73,10 +73,12 @@ extern "C" {
  * TE_INFO_PIVOT: a pivot of the LU of T - lambda_j I (partial pivoting) was
  *   below eps ||T||_1 in magnitude and was replaced by +-eps ||T||_1; common
  *   and harmless when lambda_j is accurate to a few ulps (the solve is then
- *   that of a matrix eps ||T||_1 away). */
+ *   that of a matrix eps ||T||_1 away).
+ * TE_INFO_NOCONV: see TE_STOP_GROWTH. */
 #define TE_INFO_NONFINITE 1
 #define TE_INFO_BREAKDOWN 2
 #define TE_INFO_PIVOT 4
+#define TE_INFO_NOCONV 8    /* TE_STOP_GROWTH: no solve of the vector converged */
 
 /* Re-orthogonalization inside a cluster (te_opts.orth).
  * TE_ORTH_CWY: compact WY, the paper's method (Alg. 4 with section 3.3.2).
@@ -88,6 +90,18 @@ extern "C" {
 #define TE_ORTH_MGS 1
 #define TE_MGS_MAX_N 8192
 
+/* Stop test of the repeat loop (te_opts.stop).  Alg. 1 and Alg. 4 repeat
+ * "until some condition is met" without naming it.
+ * TE_STOP_FIXED: a fixed number of iterations, te_opts.iters (default 3).
+ * TE_STOP_GROWTH: in the manner of the inverse-iteration code the paper
+ *   starts from: a solve (T - lambda I) x = v with ||v||_2 = 1 has converged
+ *   when ||x||_2 >= 1 / (n eps ||T||_1) (1/||x||_2 is the residual of
+ *   x/||x||_2; ||x||^2 summed from the last row up); the first converged
+ *   solve is followed by 2 more iterations, 5 at most.  A vector none of
+ *   whose solves converged gets TE_INFO_NOCONV. */
+#define TE_STOP_FIXED 0
+#define TE_STOP_GROWTH 1
+
 /* Options for the _ex entry point.  Zero-initialize and set what you need;
  * a zero field means the default. */
 typedef struct te_opts {
@@ -96,7 +110,8 @@ typedef struct te_opts {
     uint64_t seed;      /* start-vector seed (default TE_DEFAULT_SEED)              */
     double cluster_rtol;/* cluster gap as a multiple of ||T||_1 (default 1e-3)      */
     int coop_wgs;       /* cap on cooperative workgroups (0: fill the device)       */
-    int _reserved1;
+    int stop;           /* TE_STOP_FIXED (default): `iters` iterations per vector;
+                           TE_STOP_GROWTH: the growth rule below (iters unused)     */
     uint64_t ws_budget; /* device workspace budget in bytes for batched calls
                            (0: half the free device memory, at most 64 GiB)         */
 } te_opts;

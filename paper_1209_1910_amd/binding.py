@@ -19,7 +19,8 @@ TE_DEFAULT_SEED = 0x12091910
 TE_ORTH_CWY, TE_ORTH_MGS = 0, 1        # te_opts.orth: compact WY (Alg. 4) or MGS (Alg. 1)
 TE_MGS_MAX_N = 8192
 TE_ERR_UNSUPPORTED = -1004
-TE_INFO_NONFINITE, TE_INFO_BREAKDOWN, TE_INFO_PIVOT = 1, 2, 4   # info[1 + j] status bits
+TE_INFO_NONFINITE, TE_INFO_BREAKDOWN, TE_INFO_PIVOT, TE_INFO_NOCONV = 1, 2, 4, 8  # info bits
+TE_STOP_FIXED, TE_STOP_GROWTH = 0, 1    # te_opts.stop
 SYMBOLS = ("tridiag_eigvecs", "tridiag_eigvecs_given_w", "tridiag_eigvecs_workspace_bytes",
            "tridiag_eigvecs_ex", "tridiag_eigvecs_batched", "tridiag_eigvals", "tridiag_clusters",
            "te_server_create", "te_server_submit", "te_server_poll", "te_server_wait",
@@ -42,7 +43,7 @@ class TeError(RuntimeError):
 class te_opts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("orth", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("cluster_rtol", ctypes.c_double),
-                ("coop_wgs", ctypes.c_int), ("_reserved1", ctypes.c_int),
+                ("coop_wgs", ctypes.c_int), ("stop", ctypes.c_int),
                 ("ws_budget", ctypes.c_uint64)]
 
 
@@ -141,9 +142,11 @@ def _check(fn, rc):
         raise TeError(fn, rc, lib().te_last_hip_error())
 
 
-def _opts(iters=None, seed=None, cluster_rtol=None, coop_wgs=None, ws_budget=None, orth=None):
+def _opts(iters=None, seed=None, cluster_rtol=None, coop_wgs=None, ws_budget=None, orth=None,
+          stop=None):
     o = te_opts()
     o.iters = int(iters or 0)
+    o.stop = {None: TE_STOP_FIXED, "fixed": TE_STOP_FIXED, "growth": TE_STOP_GROWTH}.get(stop, stop)
     o.orth = {None: TE_ORTH_CWY, "cwy": TE_ORTH_CWY, "mgs": TE_ORTH_MGS}.get(orth, orth)
     o.seed = int(seed or 0)
     o.cluster_rtol = float(cluster_rtol or 0.0)

@@ -259,6 +259,7 @@ Resolved resolve(const te_opts *o) {
   if (o) {
     r.orth = o->orth;
     if (o->iters > 0) r.iters = o->iters;
+    if (o->stop == TE_STOP_GROWTH) r.iters = -1;   // the kernels' encoding of the growth rule
     if (o->seed) r.seed = o->seed;
     if (o->cluster_rtol > 0.0) r.rtol = o->cluster_rtol;
     if (o->coop_wgs > 0) r.coop_wgs = o->coop_wgs;
@@ -695,7 +696,8 @@ int batch_descs(const double *d_all, const double *e_all, const int64_t *off, co
   if (!zoff) return -9;
   if (B < 1) return -10;
   if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
-              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return -11;
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS) ||
+              (opt->stop != TE_STOP_FIXED && opt->stop != TE_STOP_GROWTH))) return -11;
   pd.assign((size_t)B, ProblemDesc{});
   bool any_e = false;
   for (int b = 0; b < B; b++) {
@@ -1113,7 +1115,8 @@ int tridiag_eigvecs_ex(const double *d, const double *e, int n, int il, int iu,
   if (!Z) return -8;
   if (ldz < n) return -9;
   if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
-              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return -10;
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS) ||
+              (opt->stop != TE_STOP_FIXED && opt->stop != TE_STOP_GROWTH))) return -10;
   if (!ws) return -11;
   if (ws_bytes < tridiag_eigvecs_workspace_bytes(n, il, iu)) return -12;
   if (((uintptr_t)ws) % kAlign) return -11;
@@ -1173,7 +1176,8 @@ int tridiag_eigvecs_noalloc(const double *d, const double *e, int n, int il, int
   if (!Z) return -8;
   if (ldz < n) return -9;
   if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
-              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return -10;
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS) ||
+              (opt->stop != TE_STOP_FIXED && opt->stop != TE_STOP_GROWTH))) return -10;
   const size_t need = tridiag_eigvecs_noalloc_bytes(n, il, iu);
   if (need > TE_NOALLOC_SCRATCH_BYTES) return TE_ERR_WORKSPACE;
   int dev = -1;
@@ -1207,7 +1211,8 @@ int tridiag_eigvecs_split(const double *d, const double *e, int n, int il, int i
   if (!Z) return -7;
   if (ldz < n) return -8;
   if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
-              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return -9;
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS) ||
+              (opt->stop != TE_STOP_FIXED && opt->stop != TE_STOP_GROWTH))) return -9;
   if (limits().device < 0) return TE_ERR_NO_DEVICE;
   const int m = iu - il + 1;
   OwnedBlocks owned(stream);
@@ -1367,7 +1372,8 @@ int bidiag_svd(const double *a, const double *b, int n, int il, int iu, double *
   if (!V) return -9;
   if (ldv < n) return -10;
   if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
-              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return -11;
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS) ||
+              (opt->stop != TE_STOP_FIXED && opt->stop != TE_STOP_GROWTH))) return -11;
   if (limits().device < 0) return TE_ERR_NO_DEVICE;
   const int N = 2 * n, m = iu - il + 1;
   OwnedBlocks owned(stream);

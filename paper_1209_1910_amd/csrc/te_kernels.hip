@@ -104,6 +104,16 @@ __device__ __forceinline__ double start_entry(uint64_t seed, uint64_t k, uint32_
   return 2.0 * u - 1.0;
 }
 
+// The growth stop rule (the kernels' iteration argument is negative): a solve
+// (T - lambda I) x = v with ||v||_2 = 1 has converged when
+// ||x||_2 >= 1 / (n eps ||T||_1) (1/||x||_2 is the residual of x/||x||_2), with
+// ||x||_2^2 summed from the last row up; the first converged solve is followed
+// by kStopExtra more iterations, kStopMaxIts at most.
+constexpr int kStopExtra = 2, kStopMaxIts = 5;
+__device__ __forceinline__ bool growth_converged(double nrm, int n, double norm1) {
+  return nrm * (((double)n * DBL_EPSILON) * norm1) >= 1.0;
+}
+
 // ---------------------------------------------------------------------------
 // a1: norm, tolerance, pivot floors and bisection bracket (one WG / problem)
 // ---------------------------------------------------------------------------
@@ -372,7 +382,9 @@ __global__ void __launch_bounds__(256) k_invit(const Prob *__restrict__ probs, i
   unsigned char *__restrict__ SW = P.Lsw + j;
   const double sigma = P.W[j];
   const double pivthr = P.prm->pivthr;
-  const int K = P.pos[j] == 0 ? iters : 1;
+  const bool stop = iters < 0, own = P.pos[j] == 0;   // own: all iterations here
+  int K = own ? (stop ? kStopMaxIts : iters) : 1;
+  bool conv = false;
   const uint64_t kglob = (uint64_t)(P.kbase + j);
 
   bool replaced = false;   // a pivot of the LU fell below pivthr
@@ -425,7 +437,6 @@ __global__ void __launch_bounds__(256) k_invit(const Prob *__restrict__ probs, i
       const size_t o = (size_t)(n - 1) * m;
       Ll[o] = 0.0; U1[o] = inv; U2[o] = 0.0; U3[o] = 0.0; SW[o] = 0;
       V[o] = cur * inv;
-      if (P.info) P.info[1 + j] = replaced ? TE_INFO_PIVOT : 0;
     } else {
       for (int i = 0; i < n - 1; i++) {
         const size_t o = (size_t)i * m;
@@ -450,8 +461,14 @@ __global__ void __launch_bounds__(256) k_invit(const Prob *__restrict__ probs, i
       x2 = x1;
       x1 = x;
     }
+    if (stop && own && !conv && growth_converged(sqrt(ss), n, P.prm->norm1)) {
+      conv = true;
+      K = min(K, k + kStopExtra);
+    }
   }
   P.nrm[j] = sqrt(ss);
+  if (P.info)
+    P.info[1 + j] = (replaced ? TE_INFO_PIVOT : 0) | (stop && own && !conv ? TE_INFO_NOCONV : 0);
 }
 
 hipError_t launch_invit(const Prob *probs, int nprob, const int64_t *loff, int64_t nlanes,
@@ -620,6 +637,7 @@ struct Scr {
   double *vla, *upre;              // n each (even offsets)
   double *xla, *xpla;              // mmax + 2 each (offset by the start parity)
   double *xseg;                    // n / 1024 + 2: segment partials of one column dot
+  double *misc;                    // 2: ||x||^2 of the last chain solve
 };
 
 __host__ __device__ inline size_t even_up(size_t x) { return (x + 1) & ~(size_t)1; }
@@ -655,7 +673,8 @@ __device__ inline Scr make_scr(double *base, int nmax, int mmax, int parity) {
   S.upre = p; p += nn;
   S.xla = p + parity; p += mm;
   S.xpla = p + parity; p += mm;
-  S.xseg = p;
+  S.xseg = p; p += even_up((size_t)nmax / 1024 + 2);
+  S.misc = p;   // inside the 64 doubles of slack scr_doubles adds
   return S;
 }
 
@@ -1030,8 +1049,10 @@ __device__ __forceinline__ bool ring_wait(lptr<int> w, int target, lptr<int> rin
 
 // Sweep of one full block from LDS slot cur; the ring reads run on into the
 // next block's slot nxt.  x into xb[0..63].
+// With SS, ss accumulates x_i^2 from the bottom row up (fused multiply-adds).
+template <bool SS>
 __device__ __forceinline__ void sweep_block(ldrp cur, ldrp nxt, SRow (&ring)[kSweepRing],
-                                            double &x1, double &x2, gptr<double> xb) {
+                                            double &x1, double &x2, double &ss, gptr<double> xb) {
 #pragma unroll
   for (int t = kWave - 1; t >= 0; t--) {
     const int slot = (kWave - 1 - t) % kSweepRing;
@@ -1041,6 +1062,7 @@ __device__ __forceinline__ void sweep_block(ldrp cur, ldrp nxt, SRow (&ring)[kSw
     x2 = x1;
     x1 = x;
     xb[t] = x;
+    if (SS) ss = fma(x, x, ss);
   }
 }
 
@@ -1052,9 +1074,12 @@ constexpr int kSegRows = 1024;
 
 // Consumer: the back sweep.  Block k holds rows n - 64 (k + 1) + j, j = 0..63
 // (rows below 0 are zero).  Returns false if a ring wait failed.
+// ss_out: null, or where lane 0 stores ||x||_2^2 of the solution (summed
+// from the last row up), written through for the other workgroups.
 template <int SLOTS>
 __device__ bool sweep_consume(SweepRing<SLOTS> &sr, double *v_, int n, int lane,
-                              unsigned long long *prog, unsigned long long seq, int *abort_flag) {
+                              unsigned long long *prog, unsigned long long seq, int *abort_flag,
+                              double *ss_out) {
   static_assert(kWave % kSweepRing == 0, "ring must tile a block");
   int pub_next = ((n - 1) / kSegRows) * kSegRows;   // start of the next segment to publish
   auto publish = [&](int done_lo) {                  // rows >= done_lo are final
@@ -1072,7 +1097,7 @@ __device__ bool sweep_consume(SweepRing<SLOTS> &sr, double *v_, int n, int lane,
   const int nfull = (n % kWave == 0) ? nblk : nblk - 1;
   if (!ring_wait((lptr<int>)&sr.staged[0], 1, ab, abort_flag)) return false;
   if (nblk > 1 && !ring_wait((lptr<int>)&sr.staged[1 % SLOTS], 2, ab, abort_flag)) return false;
-  double x1 = 0.0, x2 = 0.0;
+  double x1 = 0.0, x2 = 0.0, ss = 0.0;
   SRow ring[kSweepRing];
 #pragma unroll
   for (int d = 0; d < kSweepRing; d++) ring[d] = lds_row((ldrp)sr.row[0] + (kWave - 1 - d));
@@ -1083,9 +1108,14 @@ __device__ bool sweep_consume(SweepRing<SLOTS> &sr, double *v_, int n, int lane,
     if (k + 1 < nblk &&
         !ring_wait((lptr<int>)&sr.staged[(k + 1) % SLOTS], k + 2, ab, abort_flag))
       return false;
-    if (lane == 0)
-      sweep_block((ldrp)sr.row[k % SLOTS], (ldrp)sr.row[(k + 1) % SLOTS], ring, x1, x2,
-                  v + (n - kWave * (k + 1)));
+    if (lane == 0) {
+      if (ss_out)
+        sweep_block<true>((ldrp)sr.row[k % SLOTS], (ldrp)sr.row[(k + 1) % SLOTS], ring, x1, x2, ss,
+                          v + (n - kWave * (k + 1)));
+      else
+        sweep_block<false>((ldrp)sr.row[k % SLOTS], (ldrp)sr.row[(k + 1) % SLOTS], ring, x1, x2,
+                           ss, v + (n - kWave * (k + 1)));
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     if (lane == 0) __hip_atomic_store((lptr<int>)&sr.freed, k + 1, __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1101,10 +1131,12 @@ __device__ bool sweep_consume(SweepRing<SLOTS> &sr, double *v_, int n, int lane,
         x2 = x1;
         x1 = x;
         v[base + t] = x;
+        ss = fma(x, x, ss);
       }
     }
     publish(0);
   }
+  if (ss_out && lane == 0) st_dev(ss_out, ss);
   return true;
 }
 
@@ -1367,7 +1399,7 @@ constexpr int kLdsCarries = 2048;
 template <int NT>
 __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restrict__ q,
                           double *__restrict__ v, const Scr &S, double rn, bool overlap_p1,
-                          int la_parts) {
+                          int la_parts, double *ss_out) {
   const int n = cv.n;
   const int tid = threadIdx.x, lane = cx.lane, wave = cx.wave;
   constexpr int NW = NT / kWave;
@@ -1454,7 +1486,8 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
     // wave 0 sweeps, the other waves stage its rows; a failed ring wait
     // marks the ring, and the workgroup leaves together
     if (wave == 0)
-      sweep_consume<kSlots>(s_ring, v, n, lane, overlap_p1 ? prog : nullptr, seq, cx.abort_flag);
+      sweep_consume<kSlots>(s_ring, v, n, lane, overlap_p1 ? prog : nullptr, seq, cx.abort_flag,
+                            ss_out);
     else
       sweep_produce<kSlots>(s_ring, wave - 1, NW - 1, R, q, rn, S.P, S.Q, carry_lds, S.carry, SW,
                             n, lane, cx.abort_flag);
@@ -1522,16 +1555,24 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
 
   const double *vin = S.v;
   const bool overlap_p1 = cx.size > 1;
+  const bool stop = iters < 0;   // the growth rule: at least 1 + kStopExtra iterations
   // member c + 1's first step prepared during member c (needs a back sweep of
-  // member c to overlap with, hence iters >= 2, and a group to share it with)
-  const bool use_la = overlap_p1 && iters >= 2;
+  // member c to overlap with, hence two or more iterations, and a group to
+  // share it with)
+  const bool use_la = overlap_p1 && (stop || iters >= 2);
   bool x_ready = false;   // P1 already done beside the last back sweep
   bool la_ready = false;  // this member's first step prepared by the lookahead
   __shared__ double s_xpc;
   for (int c = 1; c < cv.M; c++) {
     const bool la_next = use_la && c + 1 < cv.M;
     const double *yprev = cv.Y + (size_t)(c - 1) * ldy;   // column c - 1 of Y
-    for (int k = 1; k <= iters; k++) {
+    int kend = iters;   // the last iteration of this member
+    bool conv = false;
+    if (stop) {         // the first solve ran with the parallel solves
+      conv = growth_converged(P.nrm[it.start + c], n, P.prm->norm1);
+      kend = conv ? 1 + kStopExtra : kStopMaxIts;
+    }
+    for (int k = 1; k <= kend; k++) {
       if (k == 1 && la_ready) {
         // P1-P3 from the lookahead: x_{c-1} arrived with member c - 1's last
         // step; x'_{c-1} = T[0..c-1, c-1] . x is formed by every workgroup
@@ -1688,7 +1729,7 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         }
       }
       if (!grp_sync<NT>(cx)) return false;
-      const bool last = (k == iters);
+      const bool last = (k == kend);
       // P5: t_hat = -t_j T_c s (column c of T) and x'' = T_{c+1} r
       // (row p has c - p entries: folded assignment).  Lookahead: the
       // segment dots of x_c = Y[:, c] . vla for member c + 1, one wave each
@@ -1785,12 +1826,23 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         double qn2;
         if (!grp_sumsq<NT>(cx, S.q, 0, n, qn2)) return false;
         // lookahead parts: both in the first sweep if there is only one
-        const int la_parts = !la_next ? 0 : (k == 1 ? (iters >= 3 ? 1 : 3) : (k == 2 ? 2 : 0));
-        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(qn2), overlap_p1, la_parts))
+        const int la_parts = !la_next ? 0 : (k == 1 ? (kend >= 3 ? 1 : 3) : (k == 2 ? 2 : 0));
+        const bool test = stop && !conv;
+        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(qn2), overlap_p1, la_parts,
+                           test ? S.misc : nullptr))
           return false;
         x_ready = overlap_p1;
+        if (test) {   // solve k + 1; its norm was written through before the barrier
+          const double nx =
+              sqrt(__hip_atomic_load(S.misc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          if (growth_converged(nx, n, P.prm->norm1)) {
+            conv = true;
+            kend = min(kend, k + 1 + kStopExtra);
+          }
+        }
       }
     }
+    if (stop && !conv && gtid == 0 && P.info) P.info[1 + it.start + c] |= TE_INFO_NOCONV;
     la_ready = la_next;
   }
   return true;
@@ -1895,7 +1947,13 @@ __device__ bool run_chain_mgs(Ctx &cx, const Prob &P, const ChainItem &it, const
       const int i = tid + t * NT;
       v[t] = i < n ? zc[i] : 0.0;
     }
-    for (int k = 1; k <= iters; k++) {
+    int kend = iters;   // the last iteration of this member
+    bool conv = false;
+    if (iters < 0) {    // the growth rule; the first solve ran with the parallel solves
+      conv = growth_converged(P.nrm[it.start + c], n, P.prm->norm1);
+      kend = conv ? 1 + kStopExtra : kStopMaxIts;
+    }
+    for (int k = 1; k <= kend; k++) {
       if (k > 1) {   // normalize and solve Eq. (1)
         double p = 0.0;
 #pragma unroll
@@ -1905,7 +1963,18 @@ __device__ bool run_chain_mgs(Ctx &cx, const Prob &P, const ChainItem &it, const
           p = fma(v[t], v[t], p);
         }
         const double ss = wg_sum(p);   // its barrier also orders the stores of q
-        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(ss), false, 0)) return false;
+        const bool test = iters < 0 && !conv;
+        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(ss), false, 0,
+                           test ? S.misc : nullptr))
+          return false;
+        if (test) {   // solve k
+          const double nx =
+              sqrt(__hip_atomic_load(S.misc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          if (growth_converged(nx, n, P.prm->norm1)) {
+            conv = true;
+            kend = min(kend, k + kStopExtra);
+          }
+        }
         const gptr<const double> vg = (gptr<const double>)S.v;
 #pragma unroll
         for (int t = 0; t < K; t++) {
@@ -1950,6 +2019,7 @@ __device__ bool run_chain_mgs(Ctx &cx, const Prob &P, const ChainItem &it, const
         }
       }
     }
+    if (iters < 0 && !conv && tid == 0 && P.info) P.info[1 + it.start + c] |= TE_INFO_NOCONV;
     // z_c = v / ||v||, the unit vector later members project against
     double p = 0.0;
 #pragma unroll

@@ -227,7 +227,8 @@ extern "C" {
 te_server *te_server_create(uint64_t hbm_budget, int lanes, const te_opts *opt) {
   if (lanes < 0 || lanes > 64) return nullptr;
   if (opt && (opt->iters < 0 || opt->cluster_rtol < 0.0 || opt->coop_wgs < 0 ||
-              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS))) return nullptr;
+              (opt->orth != TE_ORTH_CWY && opt->orth != TE_ORTH_MGS) ||
+              (opt->stop != TE_STOP_FIXED && opt->stop != TE_STOP_GROWTH))) return nullptr;
   DeviceLimits lim = limits();
   if (lim.device < 0 || lim.coop <= 0 || lim.small <= 0) return nullptr;
   try {

@@ -152,6 +152,15 @@ def test_batch_graph_and_autotune_argument_errors():
     L.te_batch_graph_destroy(NULL)
 
 
+def test_stop_option_is_checked_on_the_host():
+    L = binding.lib()
+    o = binding.te_opts()
+    o.stop = 7
+    assert L.tridiag_eigvecs_ex(P, P, 10, 1, 10, NULL, P, P, 10, ctypes.byref(o), P, 1 << 40,
+                                NULL, NULL) == -10
+    assert not L.te_server_create(0, 1, ctypes.byref(o))
+
+
 def test_orth_option_is_checked_on_the_host():
     """te_opts.orth other than TE_ORTH_CWY / TE_ORTH_MGS is an invalid options
     argument (position 10 of tridiag_eigvecs_ex, 11 of the batched call)."""
