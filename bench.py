@@ -447,6 +447,11 @@ def serving_bench(count: int, qps: float, budget_gib: float, lanes: int, coop_wg
                    "hbm_budget_gib": budget_gib, "lanes": lanes, "coop_wgs": coop_wgs},
         "saturation": {"served_solves_per_s": count / span_s, "plain_solves_per_s": sat_plain,
                        "speedup_vs_plain": (count / span_s) / sat_plain,
+                       # no schedule finishes before the longest request alone
+                       # (its cluster chains are serial), so the served rate is
+                       # at most count / max(svc): this bound over the plain rate
+                       "speedup_bound": float(svc.sum() / svc.max()),
+                       "longest_request_s": float(svc.max()),
                        "served_p50_s": _pct(lat_s, 50), "served_p99_s": _pct(lat_s, 99)},
         "at_qps": {"qps": qps, "served": summ(lat_q, span_q), "plain_fifo": summ(lat_p, span_p)},
         "by_size_class": by_class,

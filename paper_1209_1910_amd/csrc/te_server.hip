@@ -34,6 +34,7 @@ using Clock = std::chrono::steady_clock;
 // Requests with at least this many per-eigenvalue entries (n * m) are heavy.
 constexpr int64_t kHeavyEntries = (int64_t)1 << 22;
 constexpr int kMaxRound = 512;        // requests per round
+constexpr double kHeavySpread = 2.0;  // size ratio of requests sharing a heavy round
 constexpr int kDefaultLanes = 3;
 
 inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -119,6 +120,14 @@ struct Server {
       q->pop_front();
       bytes = need;
       while (!q->empty() && (int)round.size() < kMaxRound) {
+        // A heavy round ends with its longest chain, which no split of the
+        // device shortens: a request joins the head's heavy round only when
+        // its size n m is within a factor kHeavySpread of the head's, so that
+        // no request of the round waits on a much longer one.
+        if (q == &heavy) {
+          const double a = (double)head->n * head->m, b = (double)q->front()->n * q->front()->m;
+          if (a > kHeavySpread * b || b > kHeavySpread * a) break;
+        }
         round.push_back(q->front());
         const size_t b = round_bytes(round);
         if (used + b > budget) {
