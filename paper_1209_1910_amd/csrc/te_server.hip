@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "te_host.h"
+#include "te_sched.h"
 
 namespace te {
 namespace {
@@ -33,8 +34,6 @@ using Clock = std::chrono::steady_clock;
 
 // Requests with at least this many per-eigenvalue entries (n * m) are heavy.
 constexpr int64_t kHeavyEntries = (int64_t)1 << 22;
-constexpr int kMaxRound = 512;        // requests per round
-constexpr double kHeavySpread = 2.0;  // size ratio of requests sharing a heavy round
 constexpr int kDefaultLanes = 3;
 
 inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -102,44 +101,19 @@ struct Server {
 
   // Under mu: take the next round, or return false when the caller must wait.
   bool form_round(std::vector<Request *> &round, size_t &bytes) {
+    auto need = [&](const std::vector<Request *> &rs) { return round_bytes(rs); };
     for (;;) {
-      if (light.empty() && heavy.empty()) return false;
-      std::deque<Request *> *q = &light;
-      if (light.empty() || (!heavy.empty() && heavy.front()->id < light.front()->id)) q = &heavy;
-      Request *head = q->front();
-      const size_t need = round_bytes({head});
-      if (need > budget) {  // can never be admitted
-        q->pop_front();
-        head->t_start = now();
-        finish({head}, TE_ERR_WORKSPACE);
+      const int r = sched_next(light, heavy, budget, used, need, round, bytes);
+      if (r == 0) return false;
+      if (r == 2) {  // can never be admitted
+        round[0]->t_start = now();
+        finish(round, TE_ERR_WORKSPACE);
         cv.notify_all();
         continue;
       }
-      if (used + need > budget) return false;
-      round.assign(1, head);
-      q->pop_front();
-      bytes = need;
-      while (!q->empty() && (int)round.size() < kMaxRound) {
-        // A heavy round ends with its longest chain, which no split of the
-        // device shortens: a request joins the head's heavy round only when
-        // its size n m is within a factor kHeavySpread of the head's, so that
-        // no request of the round waits on a much longer one.
-        if (q == &heavy) {
-          const double a = (double)head->n * head->m, b = (double)q->front()->n * q->front()->m;
-          if (a > kHeavySpread * b || b > kHeavySpread * a) break;
-        }
-        round.push_back(q->front());
-        const size_t b = round_bytes(round);
-        if (used + b > budget) {
-          round.pop_back();
-          break;
-        }
-        bytes = b;
-        q->pop_front();
-      }
       used += bytes;
       const double t = now();
-      for (Request *r : round) r->t_start = t;
+      for (Request *q : round) q->t_start = t;
       return true;
     }
   }
