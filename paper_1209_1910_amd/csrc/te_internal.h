@@ -82,7 +82,15 @@ struct ChainScratch {
 };
 
 size_t chain_scratch_doubles(int nmax, int mmax, int nwg_in_group);
-constexpr size_t kBarWords = 64;     // unsigned words of barrier state per group
+// Group barrier state, unsigned words per group: a two-level barrier (top
+// counter, kBarSubs sub-counters and release flags, each in its own 128-byte
+// line) for the whole group at 0, the sweep's progress word at kBarProg, and
+// the same barrier for ranks 1..size-1 at kBarSubRegion.
+constexpr int kBarLine = 32, kBarSubs = 16;
+constexpr int kBarTop = 0, kBarSubCnt = kBarLine, kBarSubFlag = kBarLine * (1 + kBarSubs);
+constexpr int kBarRegion = kBarLine * (1 + 2 * kBarSubs);
+constexpr int kBarProg = kBarRegion, kBarSubRegion = kBarRegion + kBarLine;
+constexpr size_t kBarWords = 2 * kBarRegion + kBarLine;
 
 // Launch helpers (te_kernels.hip).  Multi-problem kernels map a flat lane
 // index t to (problem b, index j) through loff (nprob + 1 prefix offsets).

@@ -596,6 +596,13 @@ __device__ bool grp_sync(Ctx &c) {
   // needs every wave's stores to have completed (s_waitcnt vmcnt 0, the
   // other counters at their maximum), and the counter and flag updates can
   // be relaxed: no L2 writeback per barrier.
+  //
+  // Two levels: the ranks k, k + s, k + 2 s, ... (s = min(size, kBarSubs))
+  // arrive on sub-counter k; the last of them arrives on the top counter,
+  // and the last arrival there sets every sub-group's release flag.  Each
+  // counter and flag has its own cache line: about size / s workgroups update
+  // a sub-counter and poll a flag, s update the top counter.  (One counter and
+  // one flag for all 256 workgroups cost 40 us per compact-WY step more.)
   if (c.size > 1) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
   if (c.size == 1) return true;
@@ -603,11 +610,22 @@ __device__ bool grp_sync(Ctx &c) {
   c.gen++;
   if (threadIdx.x == 0) {
     int ok = 1;
-    const unsigned old = __hip_atomic_fetch_add(c.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old + 1u == c.gen * (unsigned)c.size)
-      __hip_atomic_store(c.flag, c.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int ns = c.size < kBarSubs ? c.size : kBarSubs;
+    const int k = c.rank % ns;
+    const unsigned members = (unsigned)((c.size - k + ns - 1) / ns);
+    unsigned *sub = c.cnt + kBarSubCnt + kBarLine * k;
+    unsigned *flag = c.cnt + kBarSubFlag + kBarLine * k;
+    const unsigned old = __hip_atomic_fetch_add(sub, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1u == c.gen * members) {
+      const unsigned top =
+          __hip_atomic_fetch_add(c.cnt + kBarTop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (top + 1u == c.gen * (unsigned)ns)
+        for (int j = 0; j < ns; j++)
+          __hip_atomic_store(c.cnt + kBarSubFlag + kBarLine * j, c.gen, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
     unsigned long long spins = 0;
-    while (__hip_atomic_load(c.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < c.gen) {
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < c.gen) {
       __builtin_amdgcn_s_sleep(1);
       if ((++spins & 255ull) == 0) {
         if (__hip_atomic_load(c.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
@@ -1332,8 +1350,8 @@ __device__ Ctx la_sub(const Ctx &cx) {
   Ctx sub = cx;
   sub.rank = cx.rank - 1;
   sub.size = cx.size - 1;
-  sub.cnt = cx.cnt + 32;
-  sub.flag = cx.cnt + 48;
+  sub.cnt = cx.cnt + kBarSubRegion;
+  sub.flag = nullptr;
   sub.gen = cx.sgen;
   sub.gw = sub.rank * (NT / kWave) + cx.wave;
   sub.nw = sub.size * (NT / kWave);
@@ -1480,7 +1498,7 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
   // with the lookahead parts la_parts for member c + 1 (bit 0: stage vla, and
   // xla from the same pass; bit 1: xpla and upre, ahead of the overlapped P1
   // in a later sweep, after it when both parts share one sweep).
-  unsigned long long *prog = reinterpret_cast<unsigned long long *>(cx.cnt + 24);
+  unsigned long long *prog = reinterpret_cast<unsigned long long *>(cx.cnt + kBarProg);
   const unsigned long long seq = cx.gen;
   if (cx.rank == 0) {
     // wave 0 sweeps, the other waves stage its rows; a failed ring wait
@@ -2112,9 +2130,9 @@ hipError_t launch_chain_small_dev(const Prob *probs, const ChainItem *items, int
 
 // Large clusters: cooperative launch; workgroup w belongs to group
 // wg_group[w] and runs that group's items in order with group barriers.
-// bars holds kBarWords words per group: arrivals (word 0), release flag (16),
-// back-sweep progress (24-25), and the lookahead sub-group's arrivals (32) and
-// release flag (48).
+// bars holds kBarWords words per group: the group's two-level barrier (word
+// 0), the back-sweep progress word (kBarProg) and the barrier of ranks
+// 1..size-1 that the lookahead uses (kBarSubRegion).
 __global__ void __launch_bounds__(kCoopThreads) k_chain_coop(const Prob *__restrict__ probs,
                                                              const ChainItem *__restrict__ items,
                                                              const Group *__restrict__ groups,
@@ -2132,7 +2150,7 @@ __global__ void __launch_bounds__(kCoopThreads) k_chain_coop(const Prob *__restr
   cx.rank = (int)blockIdx.x - G.wg0;
   cx.size = G.nwg;
   cx.cnt = bars + (size_t)g * kBarWords;
-  cx.flag = bars + (size_t)g * kBarWords + 16;
+  cx.flag = nullptr;
   cx.gen = 0;
   cx.sgen = 0;
   cx.abort_flag = abort_flag;
