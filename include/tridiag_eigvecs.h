@@ -235,6 +235,20 @@ int tridiag_eigvecs_batched(const double *d_all, const double *e_all, const int6
                             double *Z_all, const int64_t *zoff, int B, const te_opts *opt,
                             hipStream_t stream);
 
+/* tridiag_eigvecs_batched with per-vector status words.  Arguments 1-11 and
+ * their error positions as for tridiag_eigvecs_batched.  info_all (device)
+ * receives, for problem b, 1 + m_b ints at info_all + ioff[b] (m_b =
+ * iu[b] - il[b] + 1) laid out as the info of tridiag_eigvecs_ex: entry 1 + j
+ * the TE_INFO_* bits of the problem's vector j, entry 0 how many of its
+ * vectors have any bit set.  ioff (host, B entries) are caller-chosen offsets;
+ * the B regions must not overlap (else -13).  Results other than info are
+ * those of tridiag_eigvecs_batched.
+ * Argument positions: 1-11 as above, info_all=12 ioff=13. */
+int tridiag_eigvecs_batched_ex(const double *d_all, const double *e_all, const int64_t *off,
+                               const int *il, const int *iu, double *W_all, const int64_t *woff,
+                               double *Z_all, const int64_t *zoff, int B, const te_opts *opt,
+                               int *info_all, const int64_t *ioff, hipStream_t stream);
+
 /* ---- Graph-captured batched path ----
  * The batched method with every step on the device, captured once into a
  * hipGraph and then run by one graph launch per call.  The chain plan that
@@ -246,9 +260,12 @@ int tridiag_eigvecs_batched(const double *d_all, const double *e_all, const int6
  * chains' sums have one fixed order whatever the workgroup size).  Since a
  * chain never spreads over several workgroups here, this path suits batches of
  * many moderate problems (the cooperative multi-workgroup chain of the other
- * entry points is not used).  The graph path runs the compact-WY method only:
- * opts with orth = TE_ORTH_MGS make te_batch_graph_create and
- * te_batch_autotune fail with TE_ERR_UNSUPPORTED. */
+ * entry points is not used).  With orth = TE_ORTH_MGS the chains run the MGS
+ * kernel (one workgroup of 512 threads per chain, as in the other entry
+ * points; problems of order n <= TE_MGS_MAX_N, else TE_ERR_UNSUPPORTED), with
+ * results bit-identical to tridiag_eigvecs_batched under the same options.
+ * te_batch_autotune tunes the compact-WY chain only (TE_ERR_UNSUPPORTED for
+ * MGS options). */
 
 /* Launch configuration of the chain kernel of the graph path.
  * chain_threads: threads per chain workgroup (256 or 512).
@@ -266,7 +283,9 @@ typedef struct te_batch_graph te_batch_graph;
  * pointers d_all, e_all, W_all, Z_all are captured: every launch reads the
  * inputs they hold at that time and writes the outputs there.  cfg (argument
  * 12) may be NULL: then the autotune table's entry for this batch's shape
- * (see te_batch_autotune) is used, else {256, the occupancy limit}.
+ * (see te_batch_autotune) is used, else {256, the occupancy limit}; for MGS
+ * options {512, the MGS kernel's occupancy limit} (a given cfg must have
+ * chain_threads = 512 there).
  * Problems are grouped into consecutive segments whose workspace fits
  * opt->ws_budget (default: half the free device memory, at most 64 GiB); the
  * segments run one after another inside the graph and share one workspace.

@@ -16,8 +16,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtridiag_eigvecs.so")
 
 TE_DEFAULT_SEED = 0x12091910
+TE_DEFAULT_ITERS = 3
 TE_ORTH_CWY, TE_ORTH_MGS = 0, 1        # te_opts.orth: compact WY (Alg. 4) or MGS (Alg. 1)
 TE_MGS_MAX_N = 8192
+TE_ERR_HIP, TE_ERR_NO_DEVICE, TE_ERR_WORKSPACE, TE_ERR_KERNEL = -1000, -1001, -1002, -1003
 TE_ERR_UNSUPPORTED = -1004
 TE_INFO_NONFINITE, TE_INFO_BREAKDOWN, TE_INFO_PIVOT, TE_INFO_NOCONV = 1, 2, 4, 8  # info bits
 TE_STOP_FIXED, TE_STOP_GROWTH = 0, 1    # te_opts.stop
@@ -28,7 +30,8 @@ SYMBOLS = ("tridiag_eigvecs", "tridiag_eigvecs_given_w", "tridiag_eigvecs_worksp
            "te_batch_graph_create", "te_batch_graph_launch", "te_batch_graph_info",
            "te_batch_graph_destroy", "te_batch_autotune",
            "te_timing_enable", "te_timing_reset", "te_timing_read", "te_last_hip_error",
-           "tridiag_eigvecs_noalloc", "tridiag_eigvecs_noalloc_bytes", "tridiag_eigvecs_split", "bidiag_svd")
+           "tridiag_eigvecs_noalloc", "tridiag_eigvecs_noalloc_bytes", "tridiag_eigvecs_split", "bidiag_svd",
+           "tridiag_eigvecs_batched_ex")
 PHASES = ("setup", "bisect", "clusters", "first_solves", "transpose", "chain_small",
           "chain_coop", "finalize")
 
@@ -79,6 +82,8 @@ def lib():
         L.tridiag_eigvecs_noalloc_bytes.restype = sz
         L.tridiag_eigvecs_batched.argtypes = [_vp, _vp, i64p, ip, ip, _vp, i64p, _vp, i64p, i,
                                               ctypes.POINTER(te_opts), _vp]
+        L.tridiag_eigvecs_batched_ex.argtypes = [_vp, _vp, i64p, ip, ip, _vp, i64p, _vp, i64p,
+                                                 i, ctypes.POINTER(te_opts), _vp, i64p, _vp]
         L.tridiag_eigvals.argtypes = [_vp, _vp, i, i, i, _vp, _vp]
         L.tridiag_clusters.argtypes = [_vp, i, ctypes.c_double, _vp, _vp, _vp, _vp]
         L.te_server_create.argtypes = [ctypes.c_uint64, i, ctypes.POINTER(te_opts)]
@@ -417,6 +422,24 @@ def tridiag_eigvecs_batched(problems, stream=None, device="cuda", **opts):
     rc = lib().tridiag_eigvecs_batched(*lay.args(), ctypes.byref(o), _stream_ptr(stream))
     _check("tridiag_eigvecs_batched", rc)
     return lay.results()
+
+
+def tridiag_eigvecs_batched_ex(problems, stream=None, device="cuda", **opts):
+    """tridiag_eigvecs_batched with status words: returns a list of
+    (W, Z, info) per problem, info (1 + m int32) laid out as for
+    tridiag_eigvecs_ex."""
+    torch = _torch()
+    lay = problems if isinstance(problems, BatchLayout) else BatchLayout(problems, device)
+    ioff = np.zeros(lay.B, dtype=np.int64)
+    ioff[1:] = np.cumsum(lay.ms + 1)[:-1]
+    info = torch.empty(int((lay.ms + 1).sum()), dtype=torch.int32, device=lay.d_all.device)
+    o = _opts(**opts)
+    rc = lib().tridiag_eigvecs_batched_ex(*lay.args(), ctypes.byref(o), _vp(info.data_ptr()),
+                                          ioff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          _stream_ptr(stream))
+    _check("tridiag_eigvecs_batched_ex", rc)
+    return [(W, Z, info[ioff[b]: ioff[b] + 1 + int(lay.ms[b])])
+            for b, (W, Z) in enumerate(lay.results())]
 
 
 class BatchGraph:

@@ -853,8 +853,12 @@ int enqueue_segment(const GraphSeg &G, const Resolved &opt, int nt, int nwg, hip
   TE_CHECK(launch_transpose(G.dprobs, G.nprob, G.nmax, G.mmax, s));
   TE_CHECK(launch_plan(G.dprobs, G.nprob, G.bins, G.items, G.nitems, s));
   TE_CHECK(launch_fill_i32(G.flags, 2, 0, s));
-  TE_CHECK(launch_chain_small_dev(G.dprobs, G.items, G.item_cap, G.nitems, G.flags + 1, G.flags,
-                                  G.scr, nwg, nt, opt.iters, s));
+  if (opt.orth == TE_ORTH_MGS)
+    TE_CHECK(launch_chain_mgs(G.dprobs, G.items, G.item_cap, G.nitems, G.flags + 1, G.flags,
+                              G.scr, nwg, opt.iters, s));
+  else
+    TE_CHECK(launch_chain_small_dev(G.dprobs, G.items, G.item_cap, G.nitems, G.flags + 1,
+                                    G.flags, G.scr, nwg, nt, opt.iters, s));
   TE_CHECK(launch_finalize(G.dprobs, G.nprob, G.dloff, G.mtotal, s));
   return 0;
 }
@@ -938,7 +942,17 @@ int per_cu_max(int device, int nt) {
   return small_max_wgs(device, nt) / ncu;
 }
 
-bool cfg_valid(int device, const te_graph_cfg &c) {
+// Resident MGS chain workgroups (kMgsThreads threads) per CU.
+int mgs_per_cu_max(int device) {
+  const int ncu = device_cus(device);
+  return ncu > 0 ? mgs_max_wgs(device) / ncu : 0;
+}
+
+// The MGS chains run in workgroups of kMgsThreads threads.
+bool cfg_valid(int device, const te_graph_cfg &c, bool mgs) {
+  if (mgs)
+    return c.chain_threads == kMgsThreads && c.chains_per_cu >= 1 &&
+           c.chains_per_cu <= mgs_per_cu_max(device);
   if (c.chain_threads != 256 && c.chain_threads != 512) return false;
   return c.chains_per_cu >= 1 && c.chains_per_cu <= per_cu_max(device, c.chain_threads);
 }
@@ -1024,7 +1038,8 @@ int build_graph(const std::vector<ProblemDesc> &pd, const Resolved &opt, const t
   return rc;
 }
 
-te_graph_cfg default_cfg(int device) {
+te_graph_cfg default_cfg(int device, bool mgs) {
+  if (mgs) return te_graph_cfg{kMgsThreads, std::max(mgs_per_cu_max(device), 1)};
   te_graph_cfg c{256, std::max(per_cu_max(device, 256), 1)};
   return c;
 }
@@ -1481,6 +1496,28 @@ int tridiag_eigvecs_batched(const double *d_all, const double *e_all, const int6
   return solve_batched(pd, resolve(opt), stream);
 }
 
+int tridiag_eigvecs_batched_ex(const double *d_all, const double *e_all, const int64_t *off,
+                               const int *il, const int *iu, double *W_all, const int64_t *woff,
+                               double *Z_all, const int64_t *zoff, int B, const te_opts *opt,
+                               int *info_all, const int64_t *ioff, hipStream_t stream) {
+  std::vector<ProblemDesc> pd;
+  const int rc = te::batch_descs(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff, B, opt, pd);
+  if (rc) return rc;
+  if (!info_all) return -12;
+  if (!ioff) return -13;
+  // the problems' status regions [ioff[b], ioff[b] + 1 + m_b) must not overlap
+  std::vector<std::pair<int64_t, int64_t>> span((size_t)B);
+  for (int b = 0; b < B; b++) {
+    if (ioff[b] < 0) return -13;
+    span[b] = {ioff[b], ioff[b] + 1 + (iu[b] - il[b] + 1)};
+  }
+  std::sort(span.begin(), span.end());
+  for (int b = 1; b < B; b++)
+    if (span[b].first < span[b - 1].second) return -13;
+  for (int b = 0; b < B; b++) pd[b].info = info_all + ioff[b];
+  return solve_batched(pd, resolve(opt), stream);
+}
+
 te_batch_graph *te_batch_graph_create(const double *d_all, const double *e_all, const int64_t *off,
                                       const int *il, const int *iu, double *W_all,
                                       const int64_t *woff, double *Z_all, const int64_t *zoff,
@@ -1491,18 +1528,22 @@ te_batch_graph *te_batch_graph_create(const double *d_all, const double *e_all, 
   try {
     std::vector<te::ProblemDesc> pd;
     r = te::batch_descs(d_all, e_all, off, il, iu, W_all, woff, Z_all, zoff, B, opt, pd);
-    if (r == 0 && opt && opt->orth != TE_ORTH_CWY) r = TE_ERR_UNSUPPORTED;
+    const bool mgs = opt && opt->orth == TE_ORTH_MGS;
+    if (r == 0 && mgs)
+      for (const auto &D : pd)
+        if (D.n > TE_MGS_MAX_N) r = TE_ERR_UNSUPPORTED;
     if (r == 0) {
       const te::DeviceLimits lim = te::limits();
-      if (lim.device < 0 || lim.small <= 0) {
+      if (lim.device < 0 || lim.small <= 0 || (mgs && lim.mgs <= 0)) {
         r = TE_ERR_NO_DEVICE;
       } else {
-        te_graph_cfg c = te::default_cfg(lim.device);
+        te_graph_cfg c = te::default_cfg(lim.device, mgs);
         te_graph_cfg t;
         if (cfg) {
-          if (!te::cfg_valid(lim.device, *cfg)) r = -12;
+          if (!te::cfg_valid(lim.device, *cfg, mgs)) r = -12;
           else c = *cfg;
-        } else if (te::tune_lookup(te::tune_key(pd), t) && te::cfg_valid(lim.device, t)) {
+        } else if (!mgs && te::tune_lookup(te::tune_key(pd), t) &&
+                   te::cfg_valid(lim.device, t, false)) {
           c = t;
         }
         if (r == 0) {

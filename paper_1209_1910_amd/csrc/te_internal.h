@@ -123,8 +123,9 @@ hipError_t launch_chain_small_dev(const Prob *probs, const ChainItem *items, int
 constexpr int kPlanBins = 64;
 hipError_t launch_plan(const Prob *probs, int nprob, int *bins, ChainItem *items, int *nitems,
                        hipStream_t s);
-// MGS chains (Alg. 1), one 512-thread workgroup per cluster; item count as
-// for launch_chain_small_dev.  Problems of order n <= TE_MGS_MAX_N.
+// MGS chains (Alg. 1), one kMgsThreads-thread workgroup per cluster; item
+// count as for launch_chain_small_dev.  Problems of order n <= TE_MGS_MAX_N.
+constexpr int kMgsThreads = 512;
 hipError_t launch_chain_mgs(const Prob *probs, const ChainItem *items, int nitems_cap,
                             const int *nitems_dev, int *counter, int *abort_flag,
                             ChainScratch scr, int nwg, int iters, hipStream_t s);

@@ -1923,7 +1923,6 @@ static const void *small_kernel(int nt) {
 // (grp_solve).  Every reduction has one fixed order (wave butterflies, then
 // the wave totals in wave order), so results do not depend on timing.
 // ---------------------------------------------------------------------------
-constexpr int kMgsThreads = 512;
 constexpr int kMgsSlots = 16;   // n <= kMgsThreads * kMgsSlots (TE_MGS_MAX_N)
 static_assert(kMgsThreads * kMgsSlots == TE_MGS_MAX_N, "MGS size limit");
 

@@ -184,23 +184,77 @@ def test_orth_option_is_checked_on_the_host():
     assert binding._opts().orth == binding.TE_ORTH_CWY
 
 
-def test_graph_path_rejects_mgs_on_the_host():
-    """The graph path runs compact WY only: MGS options fail with
-    TE_ERR_UNSUPPORTED after the argument checks, before any HIP call."""
+def test_graph_path_mgs_checks_on_the_host():
+    """The graph path takes MGS options for problems of order up to
+    TE_MGS_MAX_N (the call then goes on to the device: TE_ERR_NO_DEVICE
+    here); a larger problem fails with TE_ERR_UNSUPPORTED, and the autotuner,
+    which tunes the compact-WY chain only, rejects MGS options; all before
+    any HIP call."""
     import numpy as np
     L = binding.lib()
     i64p = ctypes.POINTER(ctypes.c_int64)
     ip = ctypes.POINTER(ctypes.c_int)
-    off = np.array([0, 10], dtype=np.int64)
-    il = np.array([1], dtype=np.int32)
-    iu = np.array([10], dtype=np.int32)
     z = np.array([0], dtype=np.int64)
-    A = (off.ctypes.data_as(i64p), il.ctypes.data_as(ip), iu.ctypes.data_as(ip), P,
-         z.ctypes.data_as(i64p), P, z.ctypes.data_as(i64p), 1)
+    il = np.array([1], dtype=np.int32)
     o = binding.te_opts()
     o.orth = binding.TE_ORTH_MGS
     rc = ctypes.c_int(0)
-    g = L.te_batch_graph_create(P, P, *A, ctypes.byref(o), None, ctypes.byref(rc))
-    assert not g and rc.value == binding.TE_ERR_UNSUPPORTED
-    assert L.te_batch_autotune(P, P, *A, ctypes.byref(o), None, None, None, 0,
-                               None) == binding.TE_ERR_UNSUPPORTED
+    for n, expect in ((10, binding.TE_ERR_NO_DEVICE),
+                      (binding.TE_MGS_MAX_N + 1, binding.TE_ERR_UNSUPPORTED)):
+        off = np.array([0, n], dtype=np.int64)
+        iu = np.array([n], dtype=np.int32)
+        A = (off.ctypes.data_as(i64p), il.ctypes.data_as(ip), iu.ctypes.data_as(ip), P,
+             z.ctypes.data_as(i64p), P, z.ctypes.data_as(i64p), 1)
+        g = L.te_batch_graph_create(P, P, *A, ctypes.byref(o), None, ctypes.byref(rc))
+        assert not g and rc.value == expect, (n, rc.value)
+        assert L.te_batch_autotune(P, P, *A, ctypes.byref(o), None, None, None, 0,
+                                   None) == binding.TE_ERR_UNSUPPORTED
+
+
+def test_batched_ex_argument_errors():
+    """tridiag_eigvecs_batched_ex checks arguments 1-11 as the batched call
+    does, then info_all (12) and ioff (13): null, negative or overlapping
+    status regions are rejected on the host."""
+    import numpy as np
+    L = binding.lib()
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    off = np.array([0, 10, 16], dtype=np.int64)
+    il = np.array([1, 2], dtype=np.int32)
+    iu = np.array([10, 6], dtype=np.int32)
+    woff = np.array([0, 10], dtype=np.int64)
+    zoff = np.array([0, 100], dtype=np.int64)
+    A = (off.ctypes.data_as(i64p), il.ctypes.data_as(ip), iu.ctypes.data_as(ip), P,
+         woff.ctypes.data_as(i64p), P, zoff.ctypes.data_as(i64p), 2)
+
+    def call(*tail, d=P):
+        return L.tridiag_eigvecs_batched_ex(d, P, *A, None, *tail, NULL)
+
+    assert call(P, np.array([0, 11], dtype=np.int64).ctypes.data_as(i64p), d=NULL) == -1
+    assert call(NULL, np.array([0, 11], dtype=np.int64).ctypes.data_as(i64p)) == -12
+    assert call(P, None) == -13
+    assert call(P, np.array([0, -1], dtype=np.int64).ctypes.data_as(i64p)) == -13
+    # problem 0 needs 11 ints [0, 11): a region starting at 10 overlaps it
+    assert call(P, np.array([0, 10], dtype=np.int64).ctypes.data_as(i64p)) == -13
+    # problem 1 needs 6 ints [0, 6): problem 0 at 5 overlaps it, at 6 it does not
+    assert call(P, np.array([5, 0], dtype=np.int64).ctypes.data_as(i64p)) == -13
+    assert call(P, np.array([6, 0], dtype=np.int64).ctypes.data_as(i64p)) == binding.TE_ERR_NO_DEVICE
+
+
+def test_binding_constants_match_the_header():
+    """Every integer #define of the public header has the same value in the
+    Python binding."""
+    src = open(HEADER).read()
+    found = 0
+    for name, val in re.findall(r"^#define\s+(TE_\w+)\s+(.+?)(?:\s*/\*.*)?$", src, flags=re.M):
+        v = val.strip()
+        m = re.fullmatch(r"\(?(-?(?:0x[0-9A-Fa-f]+|\d+))(?:ULL)?\)?", v)
+        if m:
+            expect = int(m.group(1), 0)
+        else:
+            m = re.fullmatch(r"\(\(size_t\)(\d+)\s*<<\s*(\d+)\)", v)
+            assert m, (name, v)
+            expect = int(m.group(1)) << int(m.group(2))
+        assert getattr(binding, name) == expect, name
+        found += 1
+    assert found >= 17

@@ -150,6 +150,47 @@ def test_graph_configurations_and_segments_agree():
         assert np.array_equal(W1, W0) and np.array_equal(Z1, Z0)
 
 
+@pytest.mark.parametrize("stop", ["fixed", "growth"])
+def test_graph_mgs_chains_match_eager_mgs(stop):
+    """With MGS options the graph runs the MGS chain kernel: every replay is
+    bit-identical to the host-planned batched call with the same options; a
+    chain configuration of another workgroup size is rejected (argument 12)."""
+    probs = _mixed(24, 41, 32, 600, ranges=True)
+    probs.append(G.glued_wilkinson(20, 1e-8))          # clusters of 20 and 40 members
+    opts = dict(orth="mgs") if stop == "fixed" else dict(orth="mgs", stop=B.TE_STOP_GROWTH)
+    lay0 = B.BatchLayout(probs)
+    _say(f"mgs graph ({stop}): eager")
+    B.tridiag_eigvecs_batched(lay0, **opts)
+    W0, Z0 = _snapshot(lay0)
+    lay = B.BatchLayout(probs)
+    with pytest.raises(B.TeError) as err:
+        B.BatchGraph(lay, chain_threads=256, chains_per_cu=1, **opts)
+    assert err.value.rc == -12
+    for cfg in ({}, dict(chain_threads=512, chains_per_cu=1)):
+        _say(f"mgs graph ({stop}) {cfg}")
+        with B.BatchGraph(lay, **cfg, **opts) as g:
+            assert g.info()["chain_threads"] == 512
+            for rep in range(2):
+                lay.W_all.zero_()
+                lay.Z_all.fill_(float("nan"))
+                torch.cuda.synchronize()
+                g.launch()
+                W1, Z1 = _snapshot(lay)
+                assert np.array_equal(W1, W0) and np.array_equal(Z1, Z0), (cfg, rep)
+    # the MGS result itself against the oracle's MGS on the glued problem
+    d, e = probs[-1]
+    W, Z = lay.results()[-1]
+    iters = O.STOP_GROWTH if stop == "growth" else 3
+    Wo, Zo, _ = O.eigvecs(d, e, orth=O.MGS, seed=SEED, iters=iters)
+    assert np.array_equal(W.cpu().numpy(), Wo)
+    Zg = Z.cpu().numpy().T.copy()
+    st, sz = O.clusters(Wo, O.setup(d, e).tol)
+    assert max(sz) >= 20
+    for s0, c in zip(st, sz):   # each cluster's subspace (a singleton: its line)
+        assert subspace_sin(Zg[:, s0:s0 + c], Zo[:, s0:s0 + c]) <= 1e-9, (s0, c)
+    assert residual(d, e, Wo, Zg) <= 1e-12 and orthogonality(Zg) <= 1e-11
+
+
 def test_autotune_records_and_uses_the_winner(tmp_path, monkeypatch):
     tf = tmp_path / "tune.txt"
     monkeypatch.setenv("TE_TUNE_FILE", str(tf))

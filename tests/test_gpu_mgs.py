@@ -107,13 +107,18 @@ def test_mgs_range_batched_and_repeat():
 
 
 def test_mgs_limits():
-    """n above TE_MGS_MAX_N and the graph path report TE_ERR_UNSUPPORTED
-    before any work is enqueued."""
+    """n above TE_MGS_MAX_N reports TE_ERR_UNSUPPORTED before any work is
+    enqueued, in the plain and in the graph path (there for any problem of
+    the batch); the autotuner takes compact-WY options only."""
     d, e = G.uniform_tridiag(B.TE_MGS_MAX_N + 1, 3)
     with pytest.raises(B.TeError) as err:
         B.tridiag_eigvecs_ex(d, e, 1, 4, orth="mgs")
     assert err.value.rc == B.TE_ERR_UNSUPPORTED
-    lay = B.BatchLayout([G.uniform_tridiag(64, 1)])
+    lay = B.BatchLayout([G.uniform_tridiag(64, 1), (d, e, 1, 4)])
     with pytest.raises(B.TeError) as err:
         B.BatchGraph(lay, orth="mgs")
+    assert err.value.rc == B.TE_ERR_UNSUPPORTED
+    lay = B.BatchLayout([G.uniform_tridiag(64, 1)])
+    with pytest.raises(B.TeError) as err:
+        B.batch_autotune(lay, orth="mgs")
     assert err.value.rc == B.TE_ERR_UNSUPPORTED

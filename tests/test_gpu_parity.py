@@ -219,6 +219,28 @@ def test_batched_matches_plain():
         _compare(d, e, Wg, Zg, Wo, Zo)
 
 
+def test_batched_ex_status_words():
+    """The batched call with status words: each problem's info equals the
+    oracle's status bits for that problem (exact-shift, zero-norm and ordinary
+    problems mixed in one batch, with index ranges), and W, Z are bit-identical
+    to the batched call without them."""
+    probs = [(np.array([1.0, 1.0]), np.array([1.0]), 1, 2),
+             (np.array([0.0]), np.array([]), 1, 1),
+             G.uniform_tridiag(300, 7) + (20, 140),
+             G.glued_wilkinson(24, 1e-8) + (1, 24 * 21),
+             G.laplacian_tridiag(500) + (101, 500)]
+    _say("batched_ex status words, 5 problems")
+    out = B.tridiag_eigvecs_batched_ex(probs)
+    ref = B.tridiag_eigvecs_batched(probs)
+    torch.cuda.synchronize()
+    for (d, e, il, iu), (W, Z, info), (W0, Z0) in zip(probs, out, ref):
+        _, _, _, st = O.eigvecs(d, e, il=il, iu=iu, seed=SEED, with_status=True)
+        info = info.cpu().numpy()
+        assert np.array_equal(info[1:], st), (len(d), info[1:], st)
+        assert info[0] == np.count_nonzero(st)
+        assert torch.equal(W, W0) and torch.equal(Z.nan_to_num(7.0), Z0.nan_to_num(7.0))
+
+
 def test_deterministic_repeat():
     d, e = G.glued_wilkinson(30, 1e-8)
     _say("determinism")
