@@ -1248,7 +1248,10 @@ __device__ __forceinline__ double col_dot_segmented(const double *col, const dou
 // The next iteration's P1 (x = Y_c^T v) computed while rank 0 runs the back
 // sweep: the workgroups of ranks 1..size-1 take the columns, follow the
 // sweep's published progress segment by segment (thread 0 polls, then an
-// acquire), and accumulate each column in x[l] (owned by one wave).  With v2
+// acquire), and accumulate each column (owned by one wave) from the bottom
+// segment up, the running sums of a wave's first kAcc columns in LDS (a
+// global read-modify-write per column and segment would put a memory round
+// trip on every step), writing x[l] once the column is complete.  With v2
 // given, the same pass also accumulates x2_l = Y[:, l] . v2 (the lookahead's
 // products), from the same loads.  Returns false on abort.
 template <int NT>
@@ -1260,6 +1263,8 @@ __device__ bool p1_overlapped(Ctx &cx, const CView &cv, int c, const double *v, 
   const int gw = (cx.rank - 1) * (NT / kWave) + cx.wave;
   const int nw = (cx.size - 1) * (NT / kWave);
   __shared__ int s_go;
+  constexpr int kAcc = 64;   // partial sums kept in LDS per wave
+  __shared__ double s_acc[NT / kWave][kAcc], s_acc2[NT / kWave][kAcc];
   for (int s = top; s >= 0; s--) {
     if (threadIdx.x == 0) {
       const unsigned long long target = (seq << 32) | (unsigned long long)(n - s * kSegRows);
@@ -1284,38 +1289,58 @@ __device__ bool p1_overlapped(Ctx &cx, const CView &cv, int c, const double *v, 
     }
     __syncthreads();
     if (!s_go) return false;
-    for (int l = gw; l < c; l += nw) {
+    int j = 0;
+    for (int l = gw; l < c; l += nw, j++) {
       if (s < l / kSegRows) continue;   // segment above row l
       const double *col = cv.Y + (size_t)l * cv.ldy;
+      const bool last = (s == l / kSegRows);
       if (v2) {   // both products from one read of the column segment
         const int lo = s * kSegRows > l ? s * kSegRows : l;
         const int hi = (s + 1) * kSegRows < n ? (s + 1) * kSegRows : n;
         double d, d2;
         wave_dot_pair(col, v, v2, lo, hi, cx.lane, d, d2);
         if (cx.lane == 0) {
-          st_dev(&x[l], (s == top) ? d : x[l] + d);
-          st_dev(&x2[l], (s == top) ? d2 : x2[l] + d2);
+          if (j < kAcc) {
+            const double a = (s == top) ? d : s_acc[cx.wave][j] + d;
+            const double a2 = (s == top) ? d2 : s_acc2[cx.wave][j] + d2;
+            s_acc[cx.wave][j] = a;
+            s_acc2[cx.wave][j] = a2;
+            if (last) { st_dev(&x[l], a); st_dev(&x2[l], a2); }
+          } else {
+            st_dev(&x[l], (s == top) ? d : x[l] + d);
+            st_dev(&x2[l], (s == top) ? d2 : x2[l] + d2);
+          }
         }
       } else {
         const double d = seg_dot(col, v, l, n, s, cx.lane);
-        if (cx.lane == 0) st_dev(&x[l], (s == top) ? d : x[l] + d);
+        if (cx.lane == 0) {
+          if (j < kAcc) {
+            const double a = (s == top) ? d : s_acc[cx.wave][j] + d;
+            s_acc[cx.wave][j] = a;
+            if (last) st_dev(&x[l], a);
+          } else {
+            st_dev(&x[l], (s == top) ? d : x[l] + d);
+          }
+        }
       }
     }
   }
   return true;
 }
 
-// Lookahead for member c + 1, run by ranks 1..size-1 while rank 0 does the
-// back sweeps of member c.  Member c + 1's first compact-WY step needs, with
-// v its raw first iterate (column c + 1 of Z):
+// Lookahead for member c + 1, prepared while member c iterates.  Member
+// c + 1's first compact-WY step needs, with v its raw first iterate (column
+// c + 1 of Z):
 //   x_l = Y[:, l] . v, x'_l = T[0..l, l] . x, u_i = v_i - Yhat[i, :] x'.
 // Columns 0..c-1 of Y and T do not change while member c iterates, so
 //   vla = v, xla_l = x_l and xpla_l = x'_l for l < c, and
-//   upre_i = vla_i - Yhat[i, 0..c) . xpla for rows i > c
-// are prepared in the same arithmetic the plain passes use (the terms of
-// column c follow once member c is final): in the first sweep vla is staged
-// and xla rides along the overlapped P1's reads of Y; in the second sweep
-// (or after the first, when there is only one) come xpla and upre.
+//   upre_i = (vla_i - Yhat[i, 0..c-1) . xpla) - Y[i, c-1] xpla_{c-1}, rows i > c,
+// are prepared in the same arithmetic the plain passes use (the term of
+// column c follows once member c is final; a plain first step takes the last
+// two columns apart for that reason): in the first back sweep the ranks
+// 1..size-1 stage vla and xla rides along the overlapped P1's reads of Y;
+// xpla rides along the P2 reads of T and upre along the P3 reads of Yhat of
+// member c's last step.
 // Barriers here are among the ranks taking part.  Return false on abort.
 // Row passes (P3, P6) while the cluster has few columns (c <= kShortRows):
 // a wave per row would leave most lanes idle on rows this short, so each
@@ -1345,6 +1370,34 @@ __device__ __forceinline__ double row_dot_cm(const double *Y_, size_t ldy, int i
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
+// row_dot_cm for two vectors at once, each with row_dot_cm's arithmetic.
+__device__ __forceinline__ void row_dot_cm2(const double *Y_, size_t ldy, int i, const double *x_,
+                                            const double *z_, int len, double &ox,
+                                            double &oz) {
+  const gdp Y = (gdp)Y_, x = (gdp)x_, z = (gdp)z_;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double b[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int l = 0;
+  for (; l + 8 <= len; l += 8) {
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+      const double y = Y[(size_t)(l + r) * ldy + i];
+      a[r] = fma(y, x[l + r], a[r]);
+      b[r] = fma(y, z[l + r], b[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 8; r++) {
+    if (l + r < len) {
+      const double y = Y[(size_t)(l + r) * ldy + i];
+      a[r] = fma(y, x[l + r], a[r]);
+      b[r] = fma(y, z[l + r], b[r]);
+    }
+  }
+  ox = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  oz = ((b[0] + b[1]) + (b[2] + b[3])) + ((b[4] + b[5]) + (b[6] + b[7]));
+}
+
 template <int NT>
 __device__ Ctx la_sub(const Ctx &cx) {
   Ctx sub = cx;
@@ -1369,36 +1422,6 @@ __device__ bool la_stage(Ctx &cx, const CView &cv, int c, const Scr &S) {
   return ok;
 }
 
-template <int NT>
-__device__ bool la_tpass(Ctx &cx, const CView &cv, int c, const Scr &S, bool sync_first) {
-  Ctx sub = la_sub<NT>(cx);
-  const int n = cv.n, lane = cx.lane;
-  bool ok = !sync_first || grp_sync<NT>(sub);
-  if (ok) {
-    for (int t = 0; fold_valid(sub.gw, sub.nw, t, c); t++) {
-      const int l = fold_index(sub.gw, sub.nw, t, c);
-      const double acc = wave_dot(cv.T + (size_t)l * cv.ldm, S.xla, 0, l + 1, lane);
-      if (lane == 0) st_dev(&S.xpla[l], acc);
-    }
-    ok = grp_sync<NT>(sub);
-  }
-  if (ok) {
-    // the arithmetic of P3 for member c + 1 (short rows: a thread per row)
-    if (c + 1 <= kShortRows) {
-      const int gtid = sub.rank * NT + (int)threadIdx.x, gthreads = sub.size * NT;
-      for (int i = c + 1 + gtid; i < n; i += gthreads)
-        st_dev(&S.upre[i], S.vla[i] - row_dot_cm(cv.Y, cv.ldy, i, S.xpla, c));
-    } else {
-      for (int i = c + 1 + sub.gw; i < n; i += sub.nw) {
-        const double acc = wave_dot(cv.Yr + (size_t)i * cv.ldm, S.xpla, 0, c, lane);
-        if (lane == 0) st_dev(&S.upre[i], S.vla[i] - acc);
-      }
-    }
-  }
-  cx.sgen = sub.gen;
-  return ok;
-}
-
 // Solve (T - lambda I) v = q/||q|| with the stored LU of member c.
 // rn = 1/||q|| comes from the pass that produced q.
 //  S1  the waves of the group scan 64-row chunks of the affine maps
@@ -1417,7 +1440,7 @@ constexpr int kLdsCarries = 2048;
 template <int NT>
 __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restrict__ q,
                           double *__restrict__ v, const Scr &S, double rn, bool overlap_p1,
-                          int la_parts, double *ss_out) {
+                          bool la, double *ss_out) {
   const int n = cv.n;
   const int tid = threadIdx.x, lane = cx.lane, wave = cx.wave;
   constexpr int NW = NT / kWave;
@@ -1495,9 +1518,8 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
 
   // S3: back substitution, one lane of one wave; with overlap_p1 (groups of
   // two or more workgroups) the other ranks compute the next P1 meanwhile,
-  // with the lookahead parts la_parts for member c + 1 (bit 0: stage vla, and
-  // xla from the same pass; bit 1: xpla and upre, ahead of the overlapped P1
-  // in a later sweep, after it when both parts share one sweep).
+  // and with la the lookahead's first part for member c + 1 (stage vla, and
+  // xla from the same reads of Y).
   unsigned long long *prog = reinterpret_cast<unsigned long long *>(cx.cnt + kBarProg);
   const unsigned long long seq = cx.gen;
   if (cx.rank == 0) {
@@ -1513,13 +1535,10 @@ __device__ bool grp_solve(Ctx &cx, const CView &cv, int c, const double *__restr
     if (__hip_atomic_load((lptr<int>)&s_ring.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
       return false;
   } else if (overlap_p1) {
-    const bool la1 = la_parts & 1, la2 = la_parts & 2;
-    if (la1 && !la_stage<NT>(cx, cv, c, S)) return false;
-    if (la2 && !la1 && !la_tpass<NT>(cx, cv, c, S, false)) return false;
-    if (!p1_overlapped<NT>(cx, cv, c, v, S.x, la1 ? S.vla : nullptr, la1 ? S.xla : nullptr,
+    if (la && !la_stage<NT>(cx, cv, c, S)) return false;
+    if (!p1_overlapped<NT>(cx, cv, c, v, S.x, la ? S.vla : nullptr, la ? S.xla : nullptr,
                            prog, seq))
       return false;
-    if (la2 && la1 && !la_tpass<NT>(cx, cv, c, S, true)) return false;
   }
   return grp_sync<NT>(cx);
 }
@@ -1648,7 +1667,10 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
           if (!grp_sync<NT>(cx)) return false;
         }
         // P2: x' = T_c^T x (column l has l + 1 entries: folded assignment),
-        // kColsVar columns per wave at a time while c is small (same bits)
+        // kColsVar columns per wave at a time while c is small (same bits).
+        // In the last step of a member with a lookahead the same reads of T
+        // also give xpla = T_c^T xla for member c + 1 (wave_dot's bits).
+        const bool share2 = (k == kend) && la_next;
         if (c <= kShortRows) {
           for (int t0 = 0; fold_valid(cx.gw, cx.nw, t0, c); t0 += kColsVar) {
             const double *col[kColsVar];
@@ -1674,23 +1696,72 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         } else {
           for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
             const int l = fold_index(cx.gw, cx.nw, t, c);
-            const double acc = wave_dot(cv.T + (size_t)l * ldm, S.x, 0, l + 1, lane);
-            if (lane == 0) st_dev(&S.xp[l], acc);
+            if (share2) {
+              double acc, acc2;
+              wave_dot_pair(cv.T + (size_t)l * ldm, S.x, S.xla, 0, l + 1, lane, acc, acc2);
+              if (lane == 0) { st_dev(&S.xp[l], acc); st_dev(&S.xpla[l], acc2); }
+            } else {
+              const double acc = wave_dot(cv.T + (size_t)l * ldm, S.x, 0, l + 1, lane);
+              if (lane == 0) st_dev(&S.xp[l], acc);
+            }
+          }
+        }
+        if (share2 && c <= kShortRows) {
+          for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
+            const int l = fold_index(cx.gw, cx.nw, t, c);
+            const double acc2 = wave_dot(cv.T + (size_t)l * ldm, S.xla, 0, l + 1, lane);
+            if (lane == 0) st_dev(&S.xpla[l], acc2);
           }
         }
         if (!grp_sync<NT>(cx)) return false;
         // P3: u = v_hat - Yhat_c x' over rows c..n-1, the last column's term
-        // taken apart: u_i = (v_i - Yhat[i, 0..c-1) . x') - y_{c-1,i} x'_{c-1}
+        // taken apart: u_i = (v_i - Yhat[i, 0..c-1) . x') - y_{c-1,i} x'_{c-1};
+        // a member's first step takes the last two columns apart (the
+        // lookahead's arithmetic).  In the last step of a member with a
+        // lookahead, the same reads of Yhat also give upre for member c + 1
+        // (rows c + 1..n-1, with member c + 1's choice of row path).
         const double xpc = S.xp[c - 1];
-        if (c <= kShortRows) {   // short rows: one thread per row over column-major Y
+        const bool first = (k == 1 && c >= 2);
+        const int nd = first ? c - 2 : c - 1;
+        const double *ypp = cv.Y + (size_t)(first ? c - 2 : 0) * ldy;   // column c - 2
+        const double xppc = first ? S.xp[c - 2] : 0.0;
+        const bool share = (k == kend) && la_next && !first;
+        const bool short_u = c <= kShortRows, short_la = c + 1 <= kShortRows;
+        const double xplc = share ? S.xpla[c - 1] : 0.0;
+        auto u_of = [&](int i, double acc) {
+          const double w = vin[i] - acc;
+          return first ? (w - ypp[i] * xppc) - yprev[i] * xpc : w - yprev[i] * xpc;
+        };
+        if (short_u) {   // short rows: one thread per row over column-major Y
           for (int i = c + gtid; i < n; i += gthreads) {
-            const double acc = row_dot_cm(cv.Y, ldy, i, S.xp, c - 1);
-            st_dev(&S.u[i], (vin[i] - acc) - yprev[i] * xpc);
+            if (share && short_la) {
+              double acc, acc2;
+              row_dot_cm2(cv.Y, ldy, i, S.xp, S.xpla, nd, acc, acc2);
+              st_dev(&S.u[i], u_of(i, acc));
+              if (i > c) st_dev(&S.upre[i], (S.vla[i] - acc2) - yprev[i] * xplc);
+            } else {
+              st_dev(&S.u[i], u_of(i, row_dot_cm(cv.Y, ldy, i, S.xp, nd)));
+            }
           }
         } else {
           for (int i = c + cx.gw; i < n; i += cx.nw) {
-            const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xp, 0, c - 1, lane);
-            if (lane == 0) st_dev(&S.u[i], (vin[i] - acc) - yprev[i] * xpc);
+            if (share) {
+              double acc, acc2;
+              wave_dot_pair(cv.Yr + (size_t)i * ldm, S.xp, S.xpla, 0, nd, lane, acc, acc2);
+              if (lane == 0) {
+                st_dev(&S.u[i], u_of(i, acc));
+                if (i > c) st_dev(&S.upre[i], (S.vla[i] - acc2) - yprev[i] * xplc);
+              }
+            } else {
+              const double acc = wave_dot(cv.Yr + (size_t)i * ldm, S.xp, 0, nd, lane);
+              if (lane == 0) st_dev(&S.u[i], u_of(i, acc));
+            }
+          }
+        }
+        if (share && short_u && !short_la) {   // c = kShortRows: upre by member c + 1's path
+          for (int i = c + 1 + cx.gw; i < n; i += cx.nw) {
+            const double acc2 = wave_dot(cv.Yr + (size_t)i * ldm, S.xpla, 0, nd, lane);
+            if (lane == 0) st_dev(&S.upre[i], (S.vla[i] - acc2) - yprev[i] * xplc);
           }
         }
       }
@@ -1726,9 +1797,9 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
       } else {
         for (int l = cx.gw; l < c; l += cx.nw) {
           const double *col = cv.Y + (size_t)l * ldy;
+          const double rl = col[c];   // loaded ahead of the dot's reduction
           const double acc = wave_dot(col, S.u, c + 1, n, lane);
           if (lane == 0) {
-            const double rl = col[c];
             st_dev(&S.s[l], fma(rl, yc, acc));
             st_dev(&S.r[l], rl);
           }
@@ -1843,10 +1914,10 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
         // P7: next iterate v = (T - lambda I)^{-1} q / ||q||
         double qn2;
         if (!grp_sumsq<NT>(cx, S.q, 0, n, qn2)) return false;
-        // lookahead parts: both in the first sweep if there is only one
-        const int la_parts = !la_next ? 0 : (k == 1 ? (kend >= 3 ? 1 : 3) : (k == 2 ? 2 : 0));
+        // the lookahead's first part rides along the first sweep
+        const bool la = la_next && k == 1;
         const bool test = stop && !conv;
-        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(qn2), overlap_p1, la_parts,
+        if (!grp_solve<NT>(cx, cv, c, S.q, S.v, S, 1.0 / sqrt(qn2), overlap_p1, la,
                            test ? S.misc : nullptr))
           return false;
         x_ready = overlap_p1;
