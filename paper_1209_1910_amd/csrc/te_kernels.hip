@@ -656,12 +656,13 @@ struct Scr {
   double *xla, *xpla;              // mmax + 2 each (offset by the start parity)
   double *xseg;                    // n / 1024 + 2: segment partials of one column dot
   double *misc;                    // 2: ||x||^2 of the last chain solve
+  double *tr;                      // mmax + 2: T_c r of a member's first step (parity offset)
 };
 
 __host__ __device__ inline size_t even_up(size_t x) { return (x + 1) & ~(size_t)1; }
 
 __host__ __device__ inline size_t scr_doubles(int nmax, int mmax) {
-  return even_up(7 * even_up((size_t)nmax) + 7 * even_up((size_t)mmax + 2) +
+  return even_up(7 * even_up((size_t)nmax) + 8 * even_up((size_t)mmax + 2) +
                  even_up((size_t)nmax / 64 + 8) + even_up(2 * ((size_t)nmax / 64) + 16) +
                  even_up((size_t)nmax / 1024 + 2) + 64);
 }
@@ -692,6 +693,7 @@ __device__ inline Scr make_scr(double *base, int nmax, int mmax, int parity) {
   S.xla = p + parity; p += mm;
   S.xpla = p + parity; p += mm;
   S.xseg = p; p += even_up((size_t)nmax / 1024 + 2);
+  S.tr = p + parity; p += mm;
   S.misc = p;   // inside the 64 doubles of slack scr_doubles adds
   return S;
 }
@@ -1865,10 +1867,19 @@ __device__ bool run_chain(Ctx &cx, const Prob &P, const ChainItem &it, const Scr
           st_dev(&S.xpp[p], fma(th, yc, tr));
         }
       } else {
+        // r (row c of Y_c) and T_c stay the same through a member's steps,
+        // so T_c r is formed in its first step and reused after; later steps
+        // read T against s alone.
         for (int t = 0; fold_valid(cx.gw, cx.nw, t, c); t++) {
           const int p = fold_index(cx.gw, cx.nw, t, c);
           double ts, tr;
-          wave_dot2(cv.Tr + (size_t)p * ldm + p, S.s + p, S.r + p, c - p, lane, ts, tr);
+          if (k == 1) {
+            wave_dot2(cv.Tr + (size_t)p * ldm + p, S.s + p, S.r + p, c - p, lane, ts, tr);
+            if (lane == 0) st_dev(&S.tr[p], tr);
+          } else {
+            tr = S.tr[p];
+            ts = wave_dot(cv.Tr + (size_t)p * ldm, S.s, p, c, lane);
+          }
           if (lane == 0) {
             const double th = -tj * ts;
             st_dev(&cv.T[(size_t)p + (size_t)c * ldm], th);
