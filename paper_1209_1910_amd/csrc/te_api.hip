@@ -88,6 +88,12 @@ inline size_t even(size_t x) { return (x + 1) & ~(size_t)1; }
 // A cluster goes to the cooperative kernel when its Y block (n x size doubles)
 // exceeds this many entries; smaller chains run one per workgroup.
 constexpr size_t kLargeEntries = (size_t)1 << 20;
+// When a call has no more chains than the cooperative kernel has workgroups,
+// chains from this size up join the cooperative kernel as well: one workgroup
+// per chain would leave most of the device idle while each chain's steps run
+// latency-bound in one workgroup, and the group planner spreads every
+// workgroup over the chains by cost instead.
+constexpr size_t kPromoteEntries = (size_t)1 << 17;
 
 // Per-problem sizes of the workspace pieces (bytes, each aligned).  The
 // interleaved iterate and LU factors (V, Ll, Lu1i, Lu2, Lu3) are read for the
@@ -555,6 +561,22 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
         small_cost.push_back(cost);
       }
     }
+  }
+  if (!mgs && small_items.size() + large_items.size() <= (size_t)lim.coop) {
+    std::vector<ChainItem> keep;
+    std::vector<double> keep_cost;
+    for (size_t k = 0; k < small_items.size(); k++) {
+      const ChainItem &it = small_items[k];
+      if ((size_t)it.size * (size_t)R.hp[it.prob].n >= kPromoteEntries) {
+        large_items.push_back(it);
+        large_cost.push_back(small_cost[k]);
+      } else {
+        keep.push_back(it);
+        keep_cost.push_back(small_cost[k]);
+      }
+    }
+    small_items.swap(keep);
+    small_cost.swap(keep_cost);
   }
   {  // small items longest first
     std::vector<int> idx(small_items.size());
