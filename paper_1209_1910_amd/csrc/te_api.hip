@@ -88,11 +88,13 @@ inline size_t even(size_t x) { return (x + 1) & ~(size_t)1; }
 // A cluster goes to the cooperative kernel when its Y block (n x size doubles)
 // exceeds this many entries; smaller chains run one per workgroup.
 constexpr size_t kLargeEntries = (size_t)1 << 20;
-// When a call has no more chains than the cooperative kernel has workgroups,
-// chains from this size up join the cooperative kernel as well: one workgroup
-// per chain would leave most of the device idle while each chain's steps run
-// latency-bound in one workgroup, and the group planner spreads every
-// workgroup over the chains by cost instead.
+// When a call has no chain for the cooperative kernel and no more chains than
+// that kernel has workgroups, chains from this size up go there after all:
+// one workgroup per chain would leave most of the device idle while each
+// chain's steps run latency-bound in one workgroup, and the group planner
+// spreads every workgroup over them by cost instead.  (Beside a chain that
+// needs the cooperative kernel anyway they would each take a workgroup from
+// it, which cost up to 2.9x on large calls with many mid-size clusters.)
 constexpr size_t kPromoteEntries = (size_t)1 << 17;
 
 // Per-problem sizes of the workspace pieces (bytes, each aligned).  The
@@ -562,7 +564,7 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
       }
     }
   }
-  if (!mgs && small_items.size() + large_items.size() <= (size_t)lim.coop) {
+  if (!mgs && large_items.empty() && small_items.size() <= (size_t)lim.coop) {
     std::vector<ChainItem> keep;
     std::vector<double> keep_cost;
     for (size_t k = 0; k < small_items.size(); k++) {
