@@ -394,6 +394,7 @@ def serving_bench(count: int, qps: float, budget_gib: float, lanes: int, coop_wg
 
     say("plain path, one call per request")
     svc = np.zeros(count)
+    chain_bytes = np.zeros(count)   # algorithmic bytes of each request's cluster chains
     worst = 0.0
     identical = True
     dev = torch.device("cuda:0")
@@ -404,6 +405,12 @@ def serving_bench(count: int, qps: float, budget_gib: float, lanes: int, coop_wg
         W, Z = binding.tridiag_eigvecs(d, e, r.il, r.iu)
         Wh, Zh = W.cpu().numpy(), Z.cpu().numpy()
         svc[k] = time.perf_counter() - t0
+        # the library's gap rule: 1e-3 ||T||_1 (column sums of the tridiagonal)
+        ae = np.abs(r.e)
+        col = np.abs(r.d) + np.concatenate([[0.0], ae]) + np.concatenate([ae, [0.0]])
+        _, csize = binding.tridiag_clusters(W, 1e-3 * float(col.max()))
+        chain_bytes[k] = sum(chain_alg_bytes(len(r.d), int(M)) for M in csize.cpu().numpy()
+                             if M >= 2)
         Ws, Zs = out_q[k]
         identical &= bool(np.array_equal(Wh, Ws) and np.array_equal(Zh, Zs))
         worst = max(worst, float(np.abs(Zh - Zs).max()) if Zh.size else 0.0)
@@ -452,6 +459,12 @@ def serving_bench(count: int, qps: float, budget_gib: float, lanes: int, coop_wg
                        # at most count / max(svc): this bound over the plain rate
                        "speedup_bound": float(svc.sum() / svc.max()),
                        "longest_request_s": float(svc.max()),
+                       # the trace's chains move at least this many bytes: at
+                       # 8 TB/s no schedule serves faster than hbm_bound
+                       "chain_alg_bytes": float(chain_bytes.sum()),
+                       "hbm_bound_solves_per_s": count / (float(chain_bytes.sum()) / 8e12),
+                       "served_frac_of_hbm_bound": (count / span_s)
+                       / (count / (float(chain_bytes.sum()) / 8e12)),
                        "served_p50_s": _pct(lat_s, 50), "served_p99_s": _pct(lat_s, 99)},
         "at_qps": {"qps": qps, "served": summ(lat_q, span_q), "plain_fifo": summ(lat_p, span_p)},
         "by_size_class": by_class,
