@@ -276,6 +276,25 @@ def test_chain_result_independent_of_group_size():
             assert np.array_equal(Z.cpu().numpy().T, Zp), rep
 
 
+def test_promoted_chains_match_one_workgroup_chains():
+    """A call whose clusters are all mid-size (no chain needs the cooperative
+    kernel, at most 256 chains) runs the chains of n * size >= 2^17 in the
+    cooperative kernel; inside a batch with more chains than workgroups the
+    same problem's chains run one workgroup each.  Both give the same bits,
+    and match the oracle."""
+    d, e = G.glued_wilkinson(60, 1e-8)     # n = 1260: clusters of 60 and 120
+    _say("promotion: glued60 plain vs inside a batch of 420+ chains")
+    W0, Z0 = _gpu(d, e)
+    others = [G.glued_wilkinson(2, 1e-8) for _ in range(21)]   # 21 clusters each
+    out = B.tridiag_eigvecs_batched([(d, e)] + others)
+    torch.cuda.synchronize()
+    W1, Z1 = out[0]
+    assert np.array_equal(W1.cpu().numpy(), W0)
+    assert np.array_equal(Z1.cpu().numpy().T, Z0)
+    Wo, Zo, _ = O.eigvecs(d, e, seed=SEED)
+    _compare(d, e, W0, Z0, Wo, Zo)
+
+
 @pytest.fixture(scope="module")
 def glued7980():
     d, e = G.workload_glued()
