@@ -2,18 +2,14 @@
 // can be driven by a simulated clock and executor as well as by the server.
 //
 // Requests wait in two FIFO queues, light and heavy.  The oldest waiting
-// request (smallest id) decides which queue the next round takes from and
-// heads the round; the round then takes that queue's requests in order while
-// the device memory of the rounds in flight plus this round stays within the
-// budget, up to kMaxRound.  A heavy round ends with its longest cluster chain,
-// which no split of the device shortens, so only requests whose size n m is
-// within a factor kHeavySpread of the head's join a heavy round: the others
-// (and any that would overrun the budget) are passed over and keep their
-// places in the queue.  Heavy rounds run one after another (each holds the
-// whole device), so taking every compatible request, not only the ones right
-// behind the head, is what lets heavy requests share launches.  A request
-// that needs more than the whole budget can never run: it is taken out alone
-// and reported as rejected.
+// request (smallest id) decides which queue the next round takes from; the
+// round takes that queue's requests in order while the device memory of the
+// rounds in flight plus this round stays within the budget, up to kMaxRound.
+// A heavy round ends with its longest cluster chain, which no split of the
+// device shortens, so a request joins the head's heavy round only while its
+// size n m is within a factor kHeavySpread of the head's.  A request that
+// needs more than the whole budget can never run: it is taken out alone and
+// reported as rejected.
 #pragma once
 
 #include <cstddef>
@@ -51,42 +47,19 @@ int sched_next(std::deque<R *> &light, std::deque<R *> &heavy, uint64_t budget, 
   round.push_back(head);
   q->pop_front();
   bytes = first;
-  if (q == &light) {   // light rounds: the requests right behind the head
-    while (!q->empty() && (int)round.size() < kMaxRound) {
-      round.push_back(q->front());
-      const size_t b = need(round);
-      if (used + b > budget) {
-        round.pop_back();
-        break;
-      }
-      bytes = b;
-      q->pop_front();
-    }
-    return 1;
-  }
-  // heavy rounds: every compatible request that fits, in queue order
-  const double a = (double)head->n * head->m;
-  std::deque<R *> passed;
   while (!q->empty() && (int)round.size() < kMaxRound) {
-    R *x = q->front();
-    q->pop_front();
-    const double b = (double)x->n * x->m;
-    bool take = !(a > kHeavySpread * b || b > kHeavySpread * a);
-    if (take) {
-      round.push_back(x);
-      const size_t nb = need(round);
-      if (used + nb > budget) {
-        round.pop_back();
-        take = false;
-      } else {
-        bytes = nb;
-      }
+    if (q == &heavy) {
+      const double a = (double)head->n * head->m, b = (double)q->front()->n * q->front()->m;
+      if (a > kHeavySpread * b || b > kHeavySpread * a) break;
     }
-    if (!take) passed.push_back(x);
-  }
-  while (!passed.empty()) {   // passed-over requests back in front, in order
-    q->push_front(passed.back());
-    passed.pop_back();
+    round.push_back(q->front());
+    const size_t b = need(round);
+    if (used + b > budget) {
+      round.pop_back();
+      break;
+    }
+    bytes = b;
+    q->pop_front();
   }
   return 1;
 }

@@ -72,7 +72,7 @@ int main(int argc, char **argv) {
   uint64_t used = 0;
   int next_arrival = 0, order_light = 0, order_heavy = 0, rounds = 0, multi = 0;
   double now = 0.0;
-  int64_t last_light = 0;
+  int64_t last_light = 0, last_heavy = 0;
   while (true) {
     // admit whatever can start now
     for (int l = 0; l < lanes; l++) {
@@ -94,21 +94,14 @@ int main(int argc, char **argv) {
         CHECK(bytes == need(round) && used + bytes <= budget);
         const bool hv = round[0]->heavy;
         double svc = 0.0;
-        // the head is the oldest request of its class; a round's requests
-        // are in queue order (a heavy round may pass over incompatible ones,
-        // which keep their places: none of them is older than the head)
-        const std::deque<Req *> &own = hv ? heavy : light;
-        for (const Req *w : own) CHECK(w->id > round[0]->id);
-        if (!hv) CHECK(round[0]->id > last_light);  // light rounds: FIFO
-        int64_t prev = -1;
         for (Req *q : round) {
           CHECK(q->heavy == hv);                     // one class per round
           CHECK(need1(q) <= budget);
           const double a = (double)round[0]->n * round[0]->m, b = (double)q->n * q->m;
           if (hv) CHECK(a <= te::kHeavySpread * b && b <= te::kHeavySpread * a);
-          CHECK(q->id > prev);                       // queue order within the round
-          prev = q->id;
-          if (!hv) last_light = q->id;
+          int64_t &last = hv ? last_heavy : last_light;
+          CHECK(q->id > last);                       // FIFO within the class
+          last = q->id;
           q->order = hv ? order_heavy++ : order_light++;
           q->start = now;
           svc = std::max(svc, service(q));

@@ -54,54 +54,3 @@ def test_policy_under_a_small_budget(sim):
 def test_policy_with_one_lane_and_saturation(sim):
     out = _run(sim, 200, 1000.0, 64 << 30, 1)
     assert out["multi_request_rounds"] > 0 and out["rejected"] == 0
-
-
-HEAVY_ROUND_SRC = r"""
-#include <cstdio>
-#include <deque>
-#include <vector>
-#include "te_sched.h"
-struct R { long long id; int n, m; };
-int main() {
-  // heavy queue: sizes alternate between about 1e8 and 1e7 entries (a factor
-  // 10 apart); a light request arrived last
-  std::vector<R> rs = {{1, 10000, 10000}, {2, 3000, 3000}, {3, 9000, 9000}, {4, 3200, 3200},
-                       {5, 9500, 9500}, {6, 13000, 13000}, {7, 100, 100}};
-  std::deque<R *> light, heavy;
-  for (int k = 0; k < 6; k++) heavy.push_back(&rs[k]);
-  light.push_back(&rs[6]);
-  auto need = [](const std::vector<R *> &v) {
-    size_t b = 0;
-    for (const R *r : v) b += (size_t)r->n * r->m;   // one byte per entry
-    return b;
-  };
-  std::vector<R *> round;
-  size_t bytes = 0;
-  const unsigned long long budget = 400000000ull;    // room for 1, 3, 5 but not also 6
-  int rc = te::sched_next(light, heavy, budget, 0, need, round, bytes);
-  std::printf("%d", rc);
-  for (R *r : round) std::printf(" %lld", r->id);
-  std::printf(" |");
-  for (R *r : heavy) std::printf(" %lld", r->id);
-  std::printf(" | %zu\n", bytes);
-  return 0;
-}
-"""
-
-
-def test_heavy_round_passes_over_incompatible_requests(tmp_path):
-    """A heavy round takes every queued heavy request within the size spread of
-    its head that fits the budget, in queue order; the others keep their
-    places (and their order) for the next round."""
-    if shutil.which("g++") is None:
-        pytest.skip("g++ not available")
-    src = tmp_path / "hr.cpp"
-    src.write_text(HEAVY_ROUND_SRC)
-    exe = str(tmp_path / "hr")
-    subprocess.check_call(["g++", "-O1", "-std=c++17", "-Wall", "-I", CSRC, "-o", exe, str(src)])
-    out = subprocess.run([exe], capture_output=True, text=True, timeout=60).stdout.split("|")
-    rc_round = out[0].split()
-    assert rc_round[0] == "1"
-    assert [int(x) for x in rc_round[1:]] == [1, 3, 5]        # 6 is compatible but over budget
-    assert [int(x) for x in out[1].split()] == [2, 4, 6]        # passed over, order kept
-    assert int(out[2]) == 10000 ** 2 + 9000 ** 2 + 9500 ** 2
