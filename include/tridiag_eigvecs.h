@@ -11,7 +11,8 @@
  *   - Clusters: eigenvalue j joins the cluster of j-1 when
  *     lambda_j - lambda_{j-1} <= 1e-3 ||T||_1 (section 2.1; Alg. 1 and 4).
  *   - Iteration: solve (T - lambda_j I) v^(k) = v^(k-1) (Eq. (1)) after
- *     normalizing v^(k-1), a fixed number of times (3).
+ *     normalizing v^(k-1), by default a fixed number of times (3);
+ *     te_opts.stop selects a growth-based stopping rule instead.
  *   - Within a cluster, each iterate is re-orthogonalized against the previous
  *     members with the compact WY representation, Eqs. (cwy1)-(cwy2), in the
  *     form of section 3.3.2, as Alg. 4 prescribes.
