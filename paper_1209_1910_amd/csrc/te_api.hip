@@ -88,14 +88,17 @@ inline size_t even(size_t x) { return (x + 1) & ~(size_t)1; }
 // A cluster goes to the cooperative kernel when its Y block (n x size doubles)
 // exceeds this many entries; smaller chains run one per workgroup.
 constexpr size_t kLargeEntries = (size_t)1 << 20;
-// When a call has no chain for the cooperative kernel and no more chains than
-// that kernel has workgroups, chains from this size up go there after all:
-// one workgroup per chain would leave most of the device idle while each
-// chain's steps run latency-bound in one workgroup, and the group planner
-// spreads every workgroup over them by cost instead.  (Beside a chain that
-// needs the cooperative kernel anyway they would each take a workgroup from
-// it, which cost up to 2.9x on large calls with many mid-size clusters.)
+// When a call has no more chains than the cooperative kernel has workgroups,
+// chains from this size up go there too, unless a chain that needs that
+// kernel anyway costs (size^2 n) more than kPromoteRatio times the largest of
+// them: one workgroup per chain would leave most of the device idle while
+// each chain's steps run latency-bound in one workgroup (and before the
+// cooperative launch), and the group planner spreads every workgroup over the
+// chains by cost instead.  Beside a much costlier chain they would each take
+// a workgroup from its group for little gain: that cost up to 2.9x on large
+// random matrices with a few huge clusters and many mid-size ones.
 constexpr size_t kPromoteEntries = (size_t)1 << 17;
+constexpr double kPromoteRatio = 8.0;
 
 // Per-problem sizes of the workspace pieces (bytes, each aligned).  The
 // interleaved iterate and LU factors (V, Ll, Lu1i, Lu2, Lu3) are read for the
@@ -564,7 +567,13 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
       }
     }
   }
-  if (!mgs && large_items.empty() && small_items.size() <= (size_t)lim.coop) {
+  double large_max = 0.0, promote_max = 0.0;
+  for (double c : large_cost) large_max = std::max(large_max, c);
+  for (size_t k = 0; k < small_items.size(); k++)
+    if ((size_t)small_items[k].size * (size_t)R.hp[small_items[k].prob].n >= kPromoteEntries)
+      promote_max = std::max(promote_max, small_cost[k]);
+  if (!mgs && promote_max > 0.0 && promote_max * kPromoteRatio >= large_max &&
+      small_items.size() + large_items.size() <= (size_t)lim.coop) {
     std::vector<ChainItem> keep;
     std::vector<double> keep_cost;
     for (size_t k = 0; k < small_items.size(); k++) {
