@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libtridiag_eigvecs.so")
 SOURCES = [os.path.join(CSRC, "te_kernels.hip"), os.path.join(CSRC, "te_api.hip"),
            os.path.join(CSRC, "te_server.hip")]
 HEADERS = [os.path.join(CSRC, "te_internal.h"), os.path.join(CSRC, "te_host.h"),
-           os.path.join(CSRC, "te_sched.h"),
+           os.path.join(CSRC, "te_sched.h"), os.path.join(CSRC, "te_plan.h"),
            os.path.join(ROOT, "include", "tridiag_eigvecs.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

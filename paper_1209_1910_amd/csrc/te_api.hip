@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "te_host.h"
+#include "te_plan.h"
 
 namespace te {
 
@@ -84,21 +85,6 @@ struct PhaseTimer {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 inline size_t even(size_t x) { return (x + 1) & ~(size_t)1; }
-
-// A cluster goes to the cooperative kernel when its Y block (n x size doubles)
-// exceeds this many entries; smaller chains run one per workgroup.
-constexpr size_t kLargeEntries = (size_t)1 << 20;
-// When a call has no more chains than the cooperative kernel has workgroups,
-// chains from this size up go there too, unless a chain that needs that
-// kernel anyway costs (size^2 n) more than kPromoteRatio times the largest of
-// them: one workgroup per chain would leave most of the device idle while
-// each chain's steps run latency-bound in one workgroup (and before the
-// cooperative launch), and the group planner spreads every workgroup over the
-// chains by cost instead.  Beside a much costlier chain they would each take
-// a workgroup from its group for little gain: that cost up to 2.9x on large
-// random matrices with a few huge clusters and many mid-size ones.
-constexpr size_t kPromoteEntries = (size_t)1 << 17;
-constexpr double kPromoteRatio = 8.0;
 
 // Per-problem sizes of the workspace pieces (bytes, each aligned).  The
 // interleaved iterate and LU factors (V, Ll, Lu1i, Lu2, Lu3) are read for the
@@ -550,44 +536,34 @@ int solve_problems(const std::vector<ProblemDesc> &pd, const double *W_given, co
   }
   TE_CHECK(hipStreamSynchronize(stream));
 
-  std::vector<ChainItem> small_items, large_items;
-  std::vector<double> small_cost, large_cost;
+  // chains (clusters of two or more) and the kernel each runs in (te_plan.h)
+  std::vector<ChainItem> chains;
+  std::vector<int> chain_n, chain_size;
   for (int b = 0; b < nprob; b++) {
     for (int c = 0; c < ncl[b]; c++) {
       if (csz[b][c] < 2) continue;
-      ChainItem it{b, cst[b][c], csz[b][c], 0};
-      const double cost = (double)csz[b][c] * csz[b][c] * R.hp[b].n;
-      // MGS chains all run one per workgroup
-      if (!mgs && (size_t)csz[b][c] * (size_t)R.hp[b].n >= kLargeEntries) {
-        large_items.push_back(it);
+      chains.push_back(ChainItem{b, cst[b][c], csz[b][c], 0});
+      chain_n.push_back(R.hp[b].n);
+      chain_size.push_back(csz[b][c]);
+    }
+  }
+  const std::vector<char> kern = chain_kernels(chain_n, chain_size, (size_t)lim.coop, mgs);
+  std::vector<ChainItem> small_items, large_items;
+  std::vector<double> small_cost, large_cost;
+  for (int pass = 0; pass < 2; pass++) {   // cooperative chains first, promoted ones after
+    for (size_t k = 0; k < chains.size(); k++) {
+      const double cost = (double)chain_size[k] * chain_size[k] * chain_n[k];
+      if (pass == 0 && kern[k] == kChainCoop) {
+        large_items.push_back(chains[k]);
         large_cost.push_back(cost);
-      } else {
-        small_items.push_back(it);
+      } else if (pass == 1 && kern[k] == kChainPromoted) {
+        large_items.push_back(chains[k]);
+        large_cost.push_back(cost);
+      } else if (pass == 1 && kern[k] == kChainOneWg) {
+        small_items.push_back(chains[k]);
         small_cost.push_back(cost);
       }
     }
-  }
-  double large_max = 0.0, promote_max = 0.0;
-  for (double c : large_cost) large_max = std::max(large_max, c);
-  for (size_t k = 0; k < small_items.size(); k++)
-    if ((size_t)small_items[k].size * (size_t)R.hp[small_items[k].prob].n >= kPromoteEntries)
-      promote_max = std::max(promote_max, small_cost[k]);
-  if (!mgs && promote_max > 0.0 && promote_max * kPromoteRatio >= large_max &&
-      small_items.size() + large_items.size() <= (size_t)lim.coop) {
-    std::vector<ChainItem> keep;
-    std::vector<double> keep_cost;
-    for (size_t k = 0; k < small_items.size(); k++) {
-      const ChainItem &it = small_items[k];
-      if ((size_t)it.size * (size_t)R.hp[it.prob].n >= kPromoteEntries) {
-        large_items.push_back(it);
-        large_cost.push_back(small_cost[k]);
-      } else {
-        keep.push_back(it);
-        keep_cost.push_back(small_cost[k]);
-      }
-    }
-    small_items.swap(keep);
-    small_cost.swap(keep_cost);
   }
   {  // small items longest first
     std::vector<int> idx(small_items.size());
