@@ -194,6 +194,18 @@ def batched_bench(count: int, plain_count: int, autotune: bool = True) -> int:
     t_graph = time.perf_counter() - t0
     graph_equal = bool(torch.equal(W_all, W_ref) and torch.equal(Z_all, Z_ref))
     g.close()
+    # algorithmic bytes of every problem's cluster chains (the library's gap
+    # rule, 1e-3 ||T||_1, on the computed eigenvalues)
+    W_host = W_all.cpu().numpy()
+    chain_bytes = 0.0
+    for b, (d, e, _) in enumerate(probs):
+        n = int(ns[b])
+        w = W_host[woff[b]:woff[b] + n]
+        ae = np.abs(e)
+        col = np.abs(d) + np.concatenate([[0.0], ae]) + np.concatenate([ae, [0.0]])
+        brk = np.flatnonzero(np.diff(w) > 1e-3 * float(col.max()))
+        sizes = np.diff(np.concatenate([[0], brk + 1, [n]]))
+        chain_bytes += sum(chain_alg_bytes(n, int(M)) for M in sizes if M >= 2)
     del W_ref, Z_ref
     print(f"[bench] graph launch {t_graph:.3f} s (build {t_build:.2f} s), bit-identical "
           f"{graph_equal}", file=sys.stderr, flush=True)
@@ -235,6 +247,13 @@ def batched_bench(count: int, plain_count: int, autotune: bool = True) -> int:
                   "segments": info["segments"], "device_bytes": info["device_bytes"],
                   "bit_identical_to_host_planned": graph_equal, "autotune": tune},
         "host_planned": {"solves_per_s": count / t_batched, "s": t_batched},
+        # the chains' algorithmic bytes over the chain kernel's time in the
+        # host-planned call (HIP events on its stream): the batched chains'
+        # share of the HBM roofline
+        "chains": {"alg_bytes": chain_bytes,
+                   "chain_kernel_ms": float(phases["chain_small"][0]),
+                   "alg_GBps": chain_bytes / (float(phases["chain_small"][0]) * 1e-3) / 1e9,
+                   "hbm_frac": chain_bytes / (float(phases["chain_small"][0]) * 1e-3) / 8e12},
         "plain": {"solves_per_s": count / t_plain, "s_total": t_plain,
                   "calls_timed": pc, "extrapolated": pc < count},
         "speedup_vs_plain": t_plain / t_graph,
