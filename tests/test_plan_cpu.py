@@ -2,7 +2,8 @@
 library itself uses): large chains go to the cooperative kernel; mid-size
 chains join them when the call has at most as many chains as that kernel has
 workgroups and no cooperative chain costs more than kPromoteRatio times the
-largest mid-size one; MGS chains always run one per workgroup."""
+largest mid-size one; MGS chains always run one per workgroup.  The driver
+is built with AddressSanitizer and UndefinedBehaviorSanitizer."""
 from __future__ import annotations
 
 import os
@@ -13,6 +14,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1209_1910_amd", "csrc")
+# host code only, built with g++: AddressSanitizer and UndefinedBehaviorSanitizer
+SAN = ["-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
 
 DRIVER = r"""
 #include <cstdio>
@@ -41,7 +44,7 @@ def drv(tmp_path_factory):
     src = d / "plan.cpp"
     src.write_text(DRIVER)
     exe = str(d / "plan")
-    subprocess.check_call(["g++", "-O1", "-std=c++17", "-Wall", "-I", CSRC, "-o", exe, str(src)])
+    subprocess.check_call(["g++", "-O1", "-g", "-std=c++17", "-Wall", *SAN, "-I", CSRC, "-o", exe, str(src)])
     return exe
 
 

@@ -3,7 +3,8 @@ header the server itself uses) with a virtual clock and a fake executor
 (tests/sched_sim.cpp): budget never exceeded, one class per round, FIFO
 within each class, the oldest waiting request choosing the class, heavy
 rounds within the size spread, oversize requests rejected alone, every
-other request served; latency percentiles reported."""
+other request served; latency percentiles reported.  The simulation is built
+with AddressSanitizer and UndefinedBehaviorSanitizer."""
 from __future__ import annotations
 
 import json
@@ -16,6 +17,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1209_1910_amd", "csrc")
+# host code only, built with g++: AddressSanitizer and UndefinedBehaviorSanitizer
+SAN = ["-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
 
 
 @pytest.fixture(scope="module")
@@ -24,7 +27,7 @@ def sim():
         pytest.skip("g++ not available")
     tmp = tempfile.mkdtemp()
     exe = os.path.join(tmp, "sched_sim")
-    subprocess.check_call(["g++", "-O1", "-std=c++17", "-Wall", "-I", CSRC, "-o", exe,
+    subprocess.check_call(["g++", "-O1", "-g", "-std=c++17", "-Wall", *SAN, "-I", CSRC, "-o", exe,
                            os.path.join(ROOT, "tests", "sched_sim.cpp")])
     yield exe
     shutil.rmtree(tmp)
